@@ -1,0 +1,557 @@
+// Host side of the C ABI declared in include/utf16wf.h: argument checks,
+// launch-shape selection (tuned parameters per operation and size class),
+// result initialisation, batch plans captured into HIP graphs, and the
+// thread-local error message.
+//
+// Every argument check runs before the first HIP call, so a rejected call
+// touches neither memory nor the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "../../include/utf16wf.h"
+#include "kernels.h"
+
+using namespace utf16wf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *where) {
+    return fail(UTF16WF_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------- device info
+
+constexpr int kMaxDevices = 64;
+std::atomic<int> g_cus[kMaxDevices];
+
+int current_device(int *dev) {
+    hipError_t e = hipGetDevice(dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDevice");
+    if (*dev < 0 || *dev >= kMaxDevices)
+        return fail(UTF16WF_EHIP, "device ordinal %d out of range", *dev);
+    return UTF16WF_OK;
+}
+
+int device_cus(int dev, int *cus) {
+    int c = g_cus[dev].load(std::memory_order_relaxed);
+    if (c <= 0) {
+        hipError_t e = hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipDeviceGetAttribute");
+        if (c <= 0)
+            c = 1;
+        g_cus[dev].store(c, std::memory_order_relaxed);
+    }
+    *cus = c;
+    return UTF16WF_OK;
+}
+
+// ------------------------------------------------------------ parameters
+
+constexpr int kOps = 4;
+constexpr int kClasses = 41;
+std::mutex g_param_mu;
+utf16wf_params g_params[kOps][2][kClasses];
+bool g_params_init = false;
+
+utf16wf_params default_params(int op, int batch, int cls) {
+    utf16wf_params p;
+    // Small inputs: short tiles so that enough waves exist to spread over
+    // every compute unit; large inputs: four 16-byte loads in flight per
+    // lane and a full persistent grid.
+    p.rows = (batch || cls >= 22) ? 4 : (cls >= 20 ? 2 : 1);
+    p.wg_waves = 4;
+    p.grid_per_cu = 8;
+    p.nontemporal = 0;
+    (void)op;
+    return p;
+}
+
+void init_params_locked() {
+    if (g_params_init)
+        return;
+    for (int o = 0; o < kOps; ++o)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < kClasses; ++c)
+                g_params[o][b][c] = default_params(o, b, c);
+    g_params_init = true;
+}
+
+int size_class(int64_t n) {
+    int c = 0;
+    while (c < kClasses - 1 && (n >> (c + 1)) > 0)
+        ++c;
+    return c;
+}
+
+bool params_ok(const utf16wf_params &p) {
+    const bool rows_ok = p.rows == 1 || p.rows == 2 || p.rows == 4 || p.rows == 8;
+    return rows_ok && p.wg_waves >= 1 && p.wg_waves <= 16 && p.grid_per_cu >= 1 && p.grid_per_cu <= 64 &&
+           (p.nontemporal == 0 || p.nontemporal == 1);
+}
+
+utf16wf_params get_params(int op, int batch, int64_t n) {
+    std::lock_guard<std::mutex> lk(g_param_mu);
+    init_params_locked();
+    return g_params[op][batch ? 1 : 0][size_class(n)];
+}
+
+// Launch shape for a flat call over frame units [lo, hi), or for a batch with
+// `units` (0 = unknown) units.
+LaunchShape make_shape(const utf16wf_params &p, int cus, int64_t units, int64_t first_unit) {
+    LaunchShape s;
+    s.rows = p.rows;
+    s.wg_waves = p.wg_waves;
+    s.nontemporal = p.nontemporal;
+    const int64_t max_waves = (int64_t)p.grid_per_cu * cus * p.wg_waves;
+    int64_t waves = max_waves;
+    if (units > 0) {
+        const int64_t T = 512LL * p.rows;
+        const int64_t tiles = (first_unit % T + units + T - 1) / T + 1;
+        waves = std::min<int64_t>(tiles, max_waves);
+    }
+    s.grid = (int)std::max<int64_t>(1, (waves + p.wg_waves - 1) / p.wg_waves);
+    return s;
+}
+
+// --------------------------------------------------------- workspace
+
+struct Workspace {
+    int32_t *flag = nullptr;
+};
+std::mutex g_ws_mu;
+Workspace g_ws[kMaxDevices];
+
+int workspace(int dev, Workspace **ws) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    if (!g_ws[dev].flag) {
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, 256);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipMalloc(workspace)");
+        g_ws[dev].flag = static_cast<int32_t *>(p);
+    }
+    *ws = &g_ws[dev];
+    return UTF16WF_OK;
+}
+
+// ---------------------------------------------------------- helpers
+
+inline uintptr_t addr(const void *p) { return reinterpret_cast<uintptr_t>(p); }
+
+bool overlap_not_equal(const void *a, const void *b, int64_t n_units) {
+    if (a == b || n_units <= 0)
+        return false;
+    const uintptr_t x = addr(a), y = addr(b), len = (uintptr_t)n_units * 2u;
+    return x < y + len && y < x + len;
+}
+
+int check_op(int op) {
+    if (op < 0 || op >= kOps)
+        return fail(UTF16WF_EINVAL, "unknown op %d", op);
+    return UTF16WF_OK;
+}
+
+// Flat entry shared by is / to / to_inplace / locate.
+int flat_call(int op, const uint16_t *in, uint16_t *out, int64_t n, int32_t *flag, int64_t *first,
+              int64_t *count, hipStream_t stream) {
+    int dev, cus, rc;
+    if ((rc = current_device(&dev)) != UTF16WF_OK)
+        return rc;
+    if ((rc = device_cus(dev, &cus)) != UTF16WF_OK)
+        return rc;
+    hipError_t e;
+    if (op == kOpIs) {
+        if ((e = launch_fill_i32(flag, 1, 1, stream)) != hipSuccess)
+            return hip_fail(e, "fill result");
+    } else if (op == kOpLocate) {
+        if ((e = launch_fill_i64(first, -1, 1, stream)) != hipSuccess)
+            return hip_fail(e, "fill first_bad");
+        if ((e = launch_fill_i64(count, 0, 1, stream)) != hipSuccess)
+            return hip_fail(e, "fill count");
+    }
+    if (n == 0)
+        return UTF16WF_OK;
+    const int64_t m = (int64_t)((addr(in) & 15u) >> 1);
+    KernelArgs a{};
+    a.in = in - m;
+    a.out = out ? out - m : nullptr;
+    a.lo = m;
+    a.hi = m + n;
+    a.offsets = nullptr;
+    a.nstr = 0;
+    a.shift = 0;
+    a.flag = flag;
+    a.results = nullptr;
+    a.first = first;
+    a.count = count;
+    a.scalar_store = (op == kOpTo && (addr(out) & 15u) != (addr(in) & 15u)) ? 1 : 0;
+    const LaunchShape sh = make_shape(get_params(op, 0, n), cus, n, m);
+    if ((e = launch_main(op, false, sh, a, stream)) != hipSuccess)
+        return hip_fail(e, "kernel launch");
+    return UTF16WF_OK;
+}
+
+int check_u16(const void *p, const char *name) {
+    if (addr(p) & 1u)
+        return fail(UTF16WF_EALIGN, "%s is not 2-byte aligned", name);
+    return UTF16WF_OK;
+}
+
+int batch_call(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets, int64_t nstr,
+               uint8_t *results, int64_t *first, int64_t *count, int64_t units_hint, hipStream_t stream) {
+    int rc = check_op(op);
+    if (rc != UTF16WF_OK)
+        return rc;
+    if (nstr < 0)
+        return fail(UTF16WF_EINVAL, "num_strings < 0");
+    if (units_hint < 0)
+        return fail(UTF16WF_EINVAL, "units_hint < 0");
+    if (nstr == 0)
+        return UTF16WF_OK;
+    if (!in || !offsets)
+        return fail(UTF16WF_EINVAL, "null buffer or offsets");
+    if (op == kOpTo && !out)
+        return fail(UTF16WF_EINVAL, "null output");
+    if (op == kOpToInplace && out && out != in)
+        return fail(UTF16WF_EINVAL, "in-place call with a distinct output");
+    if (op == kOpIs && !results)
+        return fail(UTF16WF_EINVAL, "null results");
+    if (op == kOpLocate && (!first || !count))
+        return fail(UTF16WF_EINVAL, "null first_bad or count");
+    if ((rc = check_u16(in, "in")) != UTF16WF_OK)
+        return rc;
+    if (out && (rc = check_u16(out, "out")) != UTF16WF_OK)
+        return rc;
+    if (addr(offsets) & 7u)
+        return fail(UTF16WF_EALIGN, "offsets not 8-byte aligned");
+    if (op == kOpLocate && ((addr(first) | addr(count)) & 7u))
+        return fail(UTF16WF_EALIGN, "first_bad/count not 8-byte aligned");
+    if (op == kOpTo && out == in)
+        op = kOpToInplace;
+
+    int dev, cus;
+    if ((rc = current_device(&dev)) != UTF16WF_OK)
+        return rc;
+    if ((rc = device_cus(dev, &cus)) != UTF16WF_OK)
+        return rc;
+    hipError_t e;
+    if (op == kOpIs) {
+        if ((e = launch_fill_u8(results, 1, nstr, stream)) != hipSuccess)
+            return hip_fail(e, "fill results");
+    } else if (op == kOpLocate) {
+        if ((e = launch_fill_i64(first, -1, nstr, stream)) != hipSuccess)
+            return hip_fail(e, "fill first_bad");
+        if ((e = launch_fill_i64(count, 0, nstr, stream)) != hipSuccess)
+            return hip_fail(e, "fill count");
+    }
+    const int64_t m = (int64_t)((addr(in) & 15u) >> 1);
+    KernelArgs a{};
+    a.in = in - m;
+    a.out = (op == kOpTo || op == kOpToInplace) ? (op == kOpToInplace ? const_cast<uint16_t *>(in) : out) - m
+                                                : nullptr;
+    a.lo = 0;
+    a.hi = 0;
+    a.offsets = offsets;
+    a.nstr = nstr;
+    a.shift = (int32_t)m;
+    a.flag = nullptr;
+    a.results = results;
+    a.first = first;
+    a.count = count;
+    a.scalar_store = (op == kOpTo && (addr(out) & 15u) != (addr(in) & 15u)) ? 1 : 0;
+    const utf16wf_params p = get_params(op, 1, units_hint > 0 ? units_hint : (int64_t)1 << 40);
+    const LaunchShape sh = make_shape(p, cus, units_hint, 0);
+    if ((e = launch_main(op, true, sh, a, stream)) != hipSuccess)
+        return hip_fail(e, "kernel launch");
+    return UTF16WF_OK;
+}
+
+struct Plan {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int device = 0;
+};
+
+}  // namespace
+
+extern "C" {
+
+int utf16wf_abi_version(void) { return 1; }
+
+const char *utf16wf_last_error(void) { return g_err.c_str(); }
+
+int utf16wf_device_cus(void) {
+    int dev, cus;
+    if (current_device(&dev) != UTF16WF_OK || device_cus(dev, &cus) != UTF16WF_OK)
+        return 0;
+    return cus;
+}
+
+int utf16_is_well_formed(const uint16_t *in, int64_t n, int32_t *result, void *stream) {
+    if (n < 0)
+        return fail(UTF16WF_EINVAL, "n < 0");
+    if (!result || (n > 0 && !in))
+        return fail(UTF16WF_EINVAL, "null pointer");
+    if (addr(result) & 3u)
+        return fail(UTF16WF_EALIGN, "result not 4-byte aligned");
+    if (n > 0 && check_u16(in, "in") != UTF16WF_OK)
+        return UTF16WF_EALIGN;
+    return flat_call(kOpIs, in, nullptr, n, result, nullptr, nullptr, (hipStream_t)stream);
+}
+
+int utf16_to_well_formed(const uint16_t *in, uint16_t *out, int64_t n, void *stream) {
+    if (n < 0)
+        return fail(UTF16WF_EINVAL, "n < 0");
+    if (n == 0)
+        return UTF16WF_OK;
+    if (!in || !out)
+        return fail(UTF16WF_EINVAL, "null pointer");
+    int rc;
+    if ((rc = check_u16(in, "in")) != UTF16WF_OK || (rc = check_u16(out, "out")) != UTF16WF_OK)
+        return rc;
+    if (overlap_not_equal(in, out, n))
+        return fail(UTF16WF_EOVERLAP, "input and output overlap without being equal");
+    const int op = (in == out) ? kOpToInplace : kOpTo;
+    return flat_call(op, in, out, n, nullptr, nullptr, nullptr, (hipStream_t)stream);
+}
+
+int utf16_to_well_formed_inplace(uint16_t *buf, int64_t n, void *stream) {
+    return utf16_to_well_formed(buf, buf, n, stream);
+}
+
+int utf16_locate_ill_formed(const uint16_t *in, int64_t n, int64_t *first_bad, int64_t *count, void *stream) {
+    if (n < 0)
+        return fail(UTF16WF_EINVAL, "n < 0");
+    if (!first_bad || !count || (n > 0 && !in))
+        return fail(UTF16WF_EINVAL, "null pointer");
+    if ((addr(first_bad) | addr(count)) & 7u)
+        return fail(UTF16WF_EALIGN, "first_bad/count not 8-byte aligned");
+    if (n > 0 && check_u16(in, "in") != UTF16WF_OK)
+        return UTF16WF_EALIGN;
+    return flat_call(kOpLocate, in, nullptr, n, nullptr, first_bad, count, (hipStream_t)stream);
+}
+
+int utf16wf_batch(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets, int64_t num_strings,
+                  uint8_t *results, int64_t *first_bad, int64_t *count, int64_t units_hint, void *stream) {
+    return batch_call(op, in, out, offsets, num_strings, results, first_bad, count, units_hint,
+                      (hipStream_t)stream);
+}
+
+int utf16_is_well_formed_batch(const uint16_t *buf, const int64_t *offsets, int64_t num_strings, uint8_t *results,
+                               void *stream) {
+    return batch_call(kOpIs, buf, nullptr, offsets, num_strings, results, nullptr, nullptr, 0, (hipStream_t)stream);
+}
+
+int utf16_to_well_formed_batch(const uint16_t *in, uint16_t *out, const int64_t *offsets, int64_t num_strings,
+                               void *stream) {
+    return batch_call(kOpTo, in, out, offsets, num_strings, nullptr, nullptr, nullptr, 0, (hipStream_t)stream);
+}
+
+int utf16_to_well_formed_batch_inplace(uint16_t *buf, const int64_t *offsets, int64_t num_strings, void *stream) {
+    return batch_call(kOpToInplace, buf, buf, offsets, num_strings, nullptr, nullptr, nullptr, 0,
+                      (hipStream_t)stream);
+}
+
+int utf16_locate_ill_formed_batch(const uint16_t *buf, const int64_t *offsets, int64_t num_strings,
+                                  int64_t *first_bad, int64_t *count, void *stream) {
+    return batch_call(kOpLocate, buf, nullptr, offsets, num_strings, nullptr, first_bad, count, 0,
+                      (hipStream_t)stream);
+}
+
+int utf16wf_validate_offsets(const int64_t *offsets, int64_t num_strings, int64_t buf_units, void *stream) {
+    if (num_strings < 0 || buf_units < 0)
+        return fail(UTF16WF_EINVAL, "negative size");
+    if (!offsets)
+        return fail(UTF16WF_EINVAL, "null offsets");
+    if (addr(offsets) & 7u)
+        return fail(UTF16WF_EALIGN, "offsets not 8-byte aligned");
+    int dev, rc;
+    if ((rc = current_device(&dev)) != UTF16WF_OK)
+        return rc;
+    Workspace *ws;
+    if ((rc = workspace(dev, &ws)) != UTF16WF_OK)
+        return rc;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if ((e = launch_fill_i32(ws->flag, 0, 1, s)) != hipSuccess)
+        return hip_fail(e, "fill flag");
+    if ((e = launch_validate(offsets, num_strings, buf_units, ws->flag, s)) != hipSuccess)
+        return hip_fail(e, "validate launch");
+    int32_t bad = 0;
+    if ((e = hipMemcpyAsync(&bad, ws->flag, sizeof bad, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return hip_fail(e, "copy flag");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, "synchronize");
+    if (bad)
+        return fail(UTF16WF_EOFFSETS, "offsets are not non-decreasing within [0, %lld]", (long long)buf_units);
+    return UTF16WF_OK;
+}
+
+int utf16wf_batch_plan_create(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets,
+                              int64_t num_strings, uint8_t *results, void *stream, void **plan) {
+    (void)stream;
+    if (!plan)
+        return fail(UTF16WF_EINVAL, "null plan pointer");
+    *plan = nullptr;
+    int rc = check_op(op);
+    if (rc != UTF16WF_OK)
+        return rc;
+    if (op == kOpLocate)
+        return fail(UTF16WF_EINVAL, "plans support is / to / to_inplace");
+    if (num_strings < 0)
+        return fail(UTF16WF_EINVAL, "num_strings < 0");
+    if (num_strings > 0) {
+        // same checks the direct call makes, before any HIP call
+        if (!in || !offsets || (op == kOpTo && !out) || (op == kOpIs && !results))
+            return fail(UTF16WF_EINVAL, "null pointer");
+        if ((rc = check_u16(in, "in")) != UTF16WF_OK || (out && (rc = check_u16(out, "out")) != UTF16WF_OK))
+            return rc;
+        if (addr(offsets) & 7u)
+            return fail(UTF16WF_EALIGN, "offsets not 8-byte aligned");
+    }
+    Plan *p = new (std::nothrow) Plan;
+    if (!p)
+        return fail(UTF16WF_ENOMEM, "plan allocation");
+    int dev;
+    if ((rc = current_device(&dev)) != UTF16WF_OK) {
+        delete p;
+        return rc;
+    }
+    p->device = dev;
+    hipStream_t cap;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        delete p;
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    rc = batch_call(op, in, out, offsets, num_strings, results, nullptr, nullptr, 0, cap);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cap, &g);
+    (void)hipStreamDestroy(cap);
+    if (rc != UTF16WF_OK || e != hipSuccess) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        delete p;
+        return rc != UTF16WF_OK ? rc : hip_fail(e, "hipStreamEndCapture");
+    }
+    p->graph = g;
+    e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        delete p;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    *plan = p;
+    return UTF16WF_OK;
+}
+
+int utf16wf_batch_plan_launch(void *plan, void *stream) {
+    if (!plan)
+        return fail(UTF16WF_EINVAL, "null plan");
+    Plan *p = static_cast<Plan *>(plan);
+    hipError_t e = hipGraphLaunch(p->exec, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGraphLaunch");
+    return UTF16WF_OK;
+}
+
+int utf16wf_batch_plan_destroy(void *plan) {
+    if (!plan)
+        return UTF16WF_OK;
+    Plan *p = static_cast<Plan *>(plan);
+    if (p->exec)
+        (void)hipGraphExecDestroy(p->exec);
+    if (p->graph)
+        (void)hipGraphDestroy(p->graph);
+    delete p;
+    return UTF16WF_OK;
+}
+
+int utf16wf_set_params(int op, int batch, int size_class_, const utf16wf_params *p) {
+    if (check_op(op) != UTF16WF_OK)
+        return UTF16WF_EINVAL;
+    if (!p || (batch != 0 && batch != 1) || size_class_ < -1 || size_class_ >= kClasses)
+        return fail(UTF16WF_EINVAL, "bad tuning key");
+    if (!params_ok(*p))
+        return fail(UTF16WF_EINVAL, "bad parameters (rows %d, wg_waves %d, grid_per_cu %d, nontemporal %d)", p->rows,
+                    p->wg_waves, p->grid_per_cu, p->nontemporal);
+    std::lock_guard<std::mutex> lk(g_param_mu);
+    init_params_locked();
+    if (size_class_ < 0) {
+        for (int c = 0; c < kClasses; ++c)
+            g_params[op][batch][c] = *p;
+    } else {
+        g_params[op][batch][size_class_] = *p;
+    }
+    return UTF16WF_OK;
+}
+
+int utf16wf_get_params(int op, int batch, int64_t n, utf16wf_params *p) {
+    if (check_op(op) != UTF16WF_OK)
+        return UTF16WF_EINVAL;
+    if (!p || (batch != 0 && batch != 1) || n < 0)
+        return fail(UTF16WF_EINVAL, "bad tuning key");
+    *p = get_params(op, batch, n);
+    return UTF16WF_OK;
+}
+
+int utf16wf_reset_params(void) {
+    std::lock_guard<std::mutex> lk(g_param_mu);
+    g_params_init = false;
+    init_params_locked();
+    return UTF16WF_OK;
+}
+
+int utf16wf_copy_units(const uint16_t *in, uint16_t *out, int64_t n, void *stream) {
+    if (n < 0)
+        return fail(UTF16WF_EINVAL, "n < 0");
+    if (n == 0)
+        return UTF16WF_OK;
+    if (!in || !out)
+        return fail(UTF16WF_EINVAL, "null pointer");
+    int rc;
+    if ((rc = check_u16(in, "in")) != UTF16WF_OK || (rc = check_u16(out, "out")) != UTF16WF_OK)
+        return rc;
+    if ((addr(in) & 15u) != (addr(out) & 15u))
+        return fail(UTF16WF_EALIGN, "copy needs equal alignment of in and out modulo 16");
+    if (in == out || overlap_not_equal(in, out, n))
+        return fail(UTF16WF_EOVERLAP, "copy buffers overlap");
+    int dev, cus;
+    if ((rc = current_device(&dev)) != UTF16WF_OK || (rc = device_cus(dev, &cus)) != UTF16WF_OK)
+        return rc;
+    const int64_t m = (int64_t)((addr(in) & 15u) >> 1);
+    const LaunchShape sh = make_shape(get_params(kOpTo, 0, n), cus, n, m);
+    hipError_t e = launch_copy(in - m, out - m, m, m + n, sh, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "copy launch");
+    return UTF16WF_OK;
+}
+
+}  // extern "C"

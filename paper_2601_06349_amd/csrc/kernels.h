@@ -1,0 +1,54 @@
+// Internal interface between the host dispatcher (api.cpp) and the device
+// kernels (kernels.hip). Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace utf16wf {
+
+enum Op : int { kOpIs = 0, kOpTo = 1, kOpToInplace = 2, kOpLocate = 3 };
+
+struct LaunchShape {
+    int rows;         // 1, 2, 4 or 8 sixteen-byte loads per lane per tile
+    int wg_waves;     // waves per workgroup, 1..16
+    int grid;         // workgroups
+    int nontemporal;  // 0/1
+};
+
+// One launch of the repair/check kernel.
+//  in, out      frame base pointers (16-byte aligned for `in`); unit u of the
+//               frame is in[u] / out[u]
+//  lo, hi       valid frame units [lo, hi) (flat calls; batch calls read them
+//               from offsets)
+//  offsets      batch: device int64[nstr + 1]; flat: nullptr
+//  shift        batch: frame unit of buffer unit 0 (0..7)
+//  flag         flat OP_IS: device int32 result (pre-set to 1)
+//  results      batch OP_IS: device uint8[nstr] (pre-set to 1)
+//  first, count OP_LOCATE: device int64 (pre-set to -1 and 0)
+//  scalar_store store unit by unit (output phase differs from input phase)
+struct KernelArgs {
+    const uint16_t *in;
+    uint16_t *out;
+    int64_t lo, hi;
+    const int64_t *offsets;
+    int64_t nstr;
+    int32_t shift;
+    int32_t *flag;
+    uint8_t *results;
+    int64_t *first;
+    int64_t *count;
+    int scalar_store;
+};
+
+hipError_t launch_main(int op, bool batch, const LaunchShape &shape, const KernelArgs &a,
+                       hipStream_t stream);
+hipError_t launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t stream);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t stream);
+hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t stream);
+hipError_t launch_copy(const uint16_t *in, uint16_t *out, int64_t lo, int64_t hi,
+                       const LaunchShape &shape, hipStream_t stream);
+hipError_t launch_validate(const int64_t *offsets, int64_t nstr, int64_t buf_units, int32_t *bad,
+                           hipStream_t stream);
+
+}  // namespace utf16wf

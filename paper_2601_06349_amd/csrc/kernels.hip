@@ -1,0 +1,560 @@
+// UTF-16 well-formedness check and repair kernels for gfx950 (CDNA4).
+//
+// What is computed (arXiv 2601.06349): unit i is mismatched when it is a high
+// surrogate whose successor is not a low surrogate, or a low surrogate whose
+// predecessor is not a high surrogate; units outside the string count as
+// non-surrogates (Sec. 1 definition; Sec. 3.1 block formulation and edge
+// cases). Repair writes U+FFFD over mismatched units (Sec. 3.1 blend).
+//
+// How it maps to the GPU. The work is a stream over HBM with a few integer
+// operations per unit, so the kernels are built for bandwidth, not for the
+// matrix cores:
+//   * A tile is R rows of 512 units handled by one wave; each lane issues one
+//     16-byte load per row (8 units), so a row is 1 KiB of contiguous,
+//     coalesced memory and a lane keeps R loads in flight.
+//   * The paper loads every block twice at a one-unit offset to see each
+//     unit's predecessor (Sec. 3.1, "lookback"). Here each unit is loaded
+//     once: the 8 units of a lane are classified into per-byte flags with
+//     SWAR on their high bytes (the top six bits decide the class, Sec. 3.3),
+//     and the one flag a lane needs from each neighbour lane comes from a
+//     wave ballot (one bit per lane), shifted by one lane on the scalar unit.
+//     Across rows the carry is bit 63 / bit 0 of the neighbouring row's
+//     ballot. Only at the two ends of a tile is a unit of context read from
+//     memory, and only when it can matter (the first unit of the tile is a
+//     low surrogate, or the last one is a high surrogate).
+//   * The presence of any mismatch in a row is one more ballot (Sec. 3.1's
+//     branchy fast path); rows without one store the loaded data unchanged,
+//     and in place they store nothing (Sec. 3.2, in-place production
+//     variant).
+//   * No loop-carried state between tiles (Sec. 3.1 discussion), so waves
+//     take contiguous runs of tiles and never communicate.
+//   * Ragged batches mark string starts in a per-wave LDS bitmap, filled from
+//     the offsets that fall inside the tile; a start cuts the pairing between
+//     a unit and its predecessor.
+#include "kernels.h"
+
+namespace utf16wf {
+namespace {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMaxWgWaves = 16;
+constexpr int64_t kRowUnits = 512;  // 64 lanes x 8 units
+constexpr uint32_t kRepl2 = 0xFFFDFFFDu;
+
+// ------------------------------------------------------------- memory ops
+
+template <bool NT>
+__device__ __forceinline__ u32x4 ld16(const uint16_t *p) {
+    const u32x4 *q = reinterpret_cast<const u32x4 *>(p);
+    if constexpr (NT)
+        return __builtin_nontemporal_load(q);
+    else
+        return *q;
+}
+
+template <bool NT>
+__device__ __forceinline__ void st16(uint16_t *p, u32x4 v) {
+    u32x4 *q = reinterpret_cast<u32x4 *>(p);
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, q);
+    else
+        *q = v;
+}
+
+__device__ __forceinline__ uint32_t unit_of(u32x4 v, int j) {
+    uint32_t d = (j < 2) ? v.x : (j < 4) ? v.y : (j < 6) ? v.z : v.w;
+    return (j & 1) ? (d >> 16) : (d & 0xFFFFu);
+}
+
+// Units u0..u0+7 with those outside [lo, hi) read as 0 (a non-surrogate).
+__device__ __forceinline__ u32x4 ld_partial(const uint16_t *in, int64_t u0, int64_t lo, int64_t hi) {
+    uint32_t w[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const int64_t a = u0 + 2 * d, b = a + 1;
+        const uint32_t x = (a >= lo && a < hi) ? (uint32_t)in[a] : 0u;
+        const uint32_t y = (b >= lo && b < hi) ? (uint32_t)in[b] : 0u;
+        w[d] = x | (y << 16);
+    }
+    return (u32x4){w[0], w[1], w[2], w[3]};
+}
+
+// Store unit j of v to out[u0 + j] when u0 + j is in [lo, hi) and byte j of
+// the 64-bit flag word `sel` has bit 7 set.
+__device__ __forceinline__ void st_partial(uint16_t *out, int64_t u0, int64_t lo, int64_t hi, u32x4 v,
+                                           uint64_t sel) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int64_t u = u0 + j;
+        if (u >= lo && u < hi && ((sel >> (8 * j + 7)) & 1))
+            out[u] = (uint16_t)unit_of(v, j);
+    }
+}
+
+// ---------------------------------------------------------- classification
+//
+// Flags are kept one byte per unit: bit 7 of byte j of a 32-bit word is the
+// flag of unit j (A = units 0..3 of a lane, B = units 4..7).
+
+// Byte j of the result is the high byte of unit j of the dwords (lo, hi).
+__device__ __forceinline__ uint32_t high_bytes(uint32_t lo_dw, uint32_t hi_dw) {
+    return __builtin_amdgcn_perm(hi_dw, lo_dw, 0x07050301u);
+}
+
+// From four high bytes: h = 0xD8..0xDB (high surrogate), l = 0xDC..0xDF.
+__device__ __forceinline__ void flags4(uint32_t hb, uint32_t &h, uint32_t &l) {
+    // A byte of x is zero exactly when its unit is a surrogate. The low three
+    // bits of every byte of x are zero, so the borrow of the zero-byte test
+    // never produces a false flag.
+    const uint32_t x = (hb & 0xF8F8F8F8u) ^ 0xD8D8D8D8u;
+    const uint32_t s = (x - 0x01010101u) & ~x & 0x80808080u;
+    l = s & (hb << 5);  // bit 2 of the high byte separates 0xDC.. from 0xD8..
+    h = s ^ l;
+}
+
+// Four bits (bit j = unit j) to byte flags (bit 7 of byte j).
+__device__ __forceinline__ uint32_t spread4(uint32_t b) {
+    return ((b & 0xFu) * 0x00204081u & 0x01010101u) << 7;
+}
+
+// Byte flags to 0xFF bytes.
+__device__ __forceinline__ uint32_t byte_mask(uint32_t f) { return f | (f - (f >> 7)); }
+
+// Replace flagged units of v with U+FFFD.
+__device__ __forceinline__ u32x4 repair(u32x4 v, uint32_t badA, uint32_t badB) {
+    const uint32_t mA = byte_mask(badA), mB = byte_mask(badB);
+    const uint32_t m0 = __builtin_amdgcn_perm(mA, mA, 0x01010000u);
+    const uint32_t m1 = __builtin_amdgcn_perm(mA, mA, 0x03030202u);
+    const uint32_t m2 = __builtin_amdgcn_perm(mB, mB, 0x01010000u);
+    const uint32_t m3 = __builtin_amdgcn_perm(mB, mB, 0x03030202u);
+    u32x4 o;
+    o.x = (v.x & ~m0) | (kRepl2 & m0);
+    o.y = (v.y & ~m1) | (kRepl2 & m1);
+    o.z = (v.z & ~m2) | (kRepl2 & m2);
+    o.w = (v.w & ~m3) | (kRepl2 & m3);
+    return o;
+}
+
+__device__ __forceinline__ bool is_high_unit(uint32_t u) { return (u & 0xFC00u) == 0xD800u; }
+__device__ __forceinline__ bool is_low_unit(uint32_t u) { return (u & 0xFC00u) == 0xDC00u; }
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// ------------------------------------------------------------ offsets
+
+// First index i in [0, len) with off[i] >= target, else len. All lanes of
+// the wave call it with the same arguments; probes 64 positions per round.
+__device__ int64_t lower_bound_wave(const int64_t *off, int64_t len, int64_t target, int lane) {
+    int64_t a = 0, b = len;  // the answer is in [a, b]
+    while (b - a > 64) {
+        const int64_t step = (b - a + 63) >> 6;
+        const int64_t idx = a + (int64_t)lane * step;
+        const bool lt = idx < b && off[idx] < target;
+        const int c = __popcll(__ballot(lt));
+        if (c == 0)
+            return a;
+        const int64_t na = a + (int64_t)(c - 1) * step + 1;
+        const int64_t nb = min(b, a + (int64_t)c * step);
+        a = na;
+        b = nb;
+    }
+    const int64_t idx = a + lane;
+    const bool lt = idx < b && off[idx] < target;
+    return a + __popcll(__ballot(lt));
+}
+
+// Last k in [a, b) with off[k] + shift <= p (requires off[a] + shift <= p),
+// clamped to a valid string index below nstr.
+__device__ __forceinline__ int64_t string_of(const int64_t *off, int64_t shift, int64_t a, int64_t b,
+                                             int64_t p, int64_t nstr) {
+    a = min(max(a, (int64_t)0), nstr - 1);
+    b = min(b, nstr);
+    while (b - a > 1) {
+        const int64_t m = (a + b) >> 1;
+        if (off[m] + shift <= p)
+            a = m;
+        else
+            b = m;
+    }
+    return a;
+}
+
+struct TileStarts {
+    int64_t kc;     // string holding unit tl (-1 if tl is before the first string)
+    int64_t knext;  // first k with off[k] + shift >= th
+    bool next;      // a string starts at unit th
+    bool inner;     // a string starts in (tl, th)
+};
+
+// Marks the string starts in [tl, th) in the wave's bitmap (bit u - tl).
+// `cursor` is the first k with off[k] + shift >= tl.
+template <int R>
+__device__ __forceinline__ TileStarts scan_starts(const int64_t *off, int64_t nstr, int64_t shift,
+                                                  int64_t cursor, int64_t tl, int64_t th, uint32_t *bm,
+                                                  int lane) {
+    constexpr int kWords = 16 * R;
+#pragma unroll
+    for (int i = 0; i < (kWords + 63) / 64; ++i) {
+        const int w = i * 64 + lane;
+        if (w < kWords)
+            bm[w] = 0u;
+    }
+    wave_lds_sync();
+    int64_t k = cursor, le = 0;
+    bool next = false, inner = false;
+    for (;;) {
+        const int64_t idx = k + lane;
+        const int64_t o = idx <= nstr ? off[idx] + shift : INT64_MAX;
+        const bool lt = o < th;
+        if (lt) {
+            // with valid offsets tl <= o < th always holds here; the test
+            // keeps malformed offsets from writing outside the bitmap
+            const int64_t rel = o - tl;
+            if (rel >= 0 && rel < 32 * kWords)
+                atomicOr(&bm[rel >> 5], 1u << (rel & 31));
+        }
+        le += __popcll(__ballot(o <= tl));
+        next = next || (__ballot(o == th) != 0);
+        inner = inner || (__ballot(o > tl && lt) != 0);
+        const int c = __popcll(__ballot(lt));
+        k += c;
+        if (c < 64)
+            break;
+    }
+    wave_lds_sync();
+    return TileStarts{cursor + le - 1, k, next, inner};
+}
+
+// ------------------------------------------------------------- the kernel
+
+template <int OP, bool BATCH, int R, bool NT, bool SS>
+__global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
+    constexpr int64_t T = kRowUnits * R;
+    constexpr int kWords = 16 * R;
+    __shared__ uint32_t s_bm[BATCH ? kMaxWgWaves * kWords : 1];
+
+    const int lane = __lane_id();
+    const int wslot = threadIdx.x >> 6;
+    const int64_t wg_waves = blockDim.x >> 6;
+    const int64_t nwaves = (int64_t)gridDim.x * wg_waves;
+    const int64_t wave = (int64_t)blockIdx.x * wg_waves + wslot;
+
+    const uint16_t *in = a.in;
+    uint16_t *out = a.out;
+    const int64_t *off = a.offsets;
+    const int64_t shift = a.shift;
+    int64_t lo = a.lo, hi = a.hi;
+    if constexpr (BATCH) {
+        lo = off[0] + shift;
+        hi = off[a.nstr] + shift;
+    }
+    if (hi <= lo)
+        return;
+    const int64_t t0 = lo / T, t1 = (hi + T - 1) / T;
+    const int64_t per = (t1 - t0 + nwaves - 1) / nwaves;
+    const int64_t tb = t0 + wave * per;
+    const int64_t te = min(tb + per, t1);
+    if (tb >= te)
+        return;
+
+    uint32_t *bm = BATCH ? s_bm + wslot * kWords : nullptr;
+    int64_t cursor = 0;
+    if constexpr (BATCH)
+        cursor = lower_bound_wave(off, a.nstr + 1, tb * T - shift, lane);
+
+    // flat OP_LOCATE accumulators
+    uint64_t loc_first = ~0ull;
+    uint32_t loc_count = 0;
+
+    for (int64_t t = tb; t < te; ++t) {
+        const int64_t tl = t * T, th = tl + T;
+        if constexpr (OP == kOpIs && !BATCH) {
+            if (__hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+                return;
+        }
+        const bool interior = tl >= lo && th <= hi;
+        u32x4 v[R];
+        TileStarts ts{0, 0, false, false};
+
+        if constexpr (BATCH && OP == kOpIs) {
+            // Check first whether the whole tile lies in a string already
+            // known to be ill-formed; then its data need not be read at all.
+            ts = scan_starts<R>(off, a.nstr, shift, cursor, tl, th, bm, lane);
+            cursor = ts.knext;
+            if (!ts.inner && ts.kc >= 0 && ts.kc < a.nstr &&
+                __hip_atomic_load(a.results + ts.kc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+                continue;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t u0 = tl + ((int64_t)r * 64 + lane) * 8;
+            if (interior)
+                v[r] = ld16<NT>(in + u0);
+            else
+                v[r] = ld_partial(in, u0, lo, hi);
+        }
+        if constexpr (BATCH && OP != kOpIs) {
+            ts = scan_starts<R>(off, a.nstr, shift, cursor, tl, th, bm, lane);
+            cursor = ts.knext;
+        }
+
+        // classify every row; ballot the two flags neighbours need
+        uint32_t hA[R], hB[R], lA[R], lB[R], sA[R], sB[R];
+        uint64_t hl[R], lf[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            flags4(high_bytes(v[r].x, v[r].y), hA[r], lA[r]);
+            flags4(high_bytes(v[r].z, v[r].w), hB[r], lB[r]);
+            if constexpr (BATCH) {
+                const uint32_t sbits = reinterpret_cast<const uint8_t *>(bm)[r * 64 + lane];
+                sA[r] = spread4(sbits);
+                sB[r] = spread4(sbits >> 4);
+            } else {
+                sA[r] = 0u;
+                sB[r] = 0u;
+            }
+            hl[r] = __ballot((hB[r] >> 31) & 1u);               // unit 7 is high
+            lf[r] = __ballot(((lA[r] & ~sA[r]) >> 7) & 1u);     // unit 0 is a low that may pair back
+        }
+
+        // one unit of context at each tile end, read only when it matters
+        uint64_t carry_in = 0, carry_nx = 0;
+        if ((lf[0] & 1ull) && tl - 1 >= lo)
+            carry_in = is_high_unit(in[tl - 1]) ? 1ull : 0ull;
+        if ((hl[R - 1] >> 63) && th < hi && !(BATCH && ts.next))
+            carry_nx = is_low_unit(in[th]) ? 1ull : 0ull;
+
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t pm = (hl[r] << 1) | (r == 0 ? carry_in : (hl[r - 1] >> 63));
+            const uint64_t nm = (lf[r] >> 1) | ((r == R - 1 ? carry_nx : (lf[r + 1] & 1ull)) << 63);
+            const uint32_t hp = (uint32_t)(pm >> lane) & 1u;
+            const uint32_t ln = (uint32_t)(nm >> lane) & 1u;
+            const uint32_t lAp = lA[r] & ~sA[r], lBp = lB[r] & ~sB[r];
+            // predecessor is high (cut at string starts) / successor is low
+            const uint32_t psA = ((hA[r] << 8) | (hp << 7)) & ~sA[r];
+            const uint32_t psB = ((hB[r] << 8) | (hA[r] >> 24)) & ~sB[r];
+            const uint32_t nsA = (lAp >> 8) | (lBp << 24);
+            const uint32_t nsB = (lBp >> 8) | (ln << 31);
+            const uint32_t badA = (hA[r] & ~nsA) | (lA[r] & ~psA);
+            const uint32_t badB = (hB[r] & ~nsB) | (lB[r] & ~psB);
+            const bool lane_bad = (badA | badB) != 0u;
+            const uint64_t wave_bad = __ballot(lane_bad);
+            const int64_t u0 = tl + ((int64_t)r * 64 + lane) * 8;
+            const uint64_t bad64 = (uint64_t)badA | ((uint64_t)badB << 32);
+
+            if constexpr (OP == kOpTo) {
+                const u32x4 o = wave_bad ? repair(v[r], badA, badB) : v[r];
+                if (interior && !SS)
+                    st16<NT>(out + u0, o);
+                else
+                    st_partial(out, u0, lo, hi, o, 0x8080808080808080ull);
+            } else if constexpr (OP == kOpToInplace) {
+                if (lane_bad) {
+                    const u32x4 o = repair(v[r], badA, badB);
+                    if (interior)
+                        st16<NT>(out + u0, o);
+                    else
+                        st_partial(out, u0, lo, hi, o, bad64);
+                }
+            } else if constexpr (OP == kOpIs) {
+                if constexpr (!BATCH) {
+                    if (wave_bad) {
+                        if (lane == 0)
+                            __hip_atomic_store(a.flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        return;
+                    }
+                } else {
+                    if (lane_bad) {
+                        uint64_t m = bad64;
+                        int64_t last_k = -1;
+                        while (m) {
+                            const int j = __builtin_ctzll(m) >> 3;
+                            m &= m - 1;
+                            const int64_t k = string_of(off, shift, ts.kc, ts.knext, u0 + j, a.nstr);
+                            if (k != last_k)
+                                __hip_atomic_store(a.results + k, (uint8_t)0, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                            last_k = k;
+                        }
+                    }
+                }
+            } else {  // kOpLocate
+                if constexpr (!BATCH) {
+                    if (wave_bad) {
+                        loc_count += (uint32_t)__popcll(bad64);
+                        if (loc_first == ~0ull) {
+                            const int fl = __builtin_ctzll(wave_bad);
+                            const int j = lane_bad ? (__builtin_ctzll(bad64) >> 3) : 0;
+                            const int jf = __shfl(j, fl);
+                            loc_first = (uint64_t)(tl + ((int64_t)r * 64 + fl) * 8 + jf - lo);
+                        }
+                    }
+                } else {
+                    if (lane_bad) {
+                        uint64_t m = bad64;
+                        while (m) {
+                            const int j = __builtin_ctzll(m) >> 3;
+                            m &= m - 1;
+                            const int64_t p = u0 + j;
+                            const int64_t k = string_of(off, shift, ts.kc, ts.knext, p, a.nstr);
+                            atomicMin(reinterpret_cast<unsigned long long *>(a.first + k),
+                                      (unsigned long long)(p - (off[k] + shift)));
+                            atomicAdd(reinterpret_cast<unsigned long long *>(a.count + k), 1ull);
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    if constexpr (OP == kOpLocate && !BATCH) {
+        uint32_t c = loc_count;
+#pragma unroll
+        for (int s = 32; s >= 1; s >>= 1)
+            c += __shfl_xor(c, s);
+        if (lane == 0 && c != 0) {
+            atomicAdd(reinterpret_cast<unsigned long long *>(a.count), (unsigned long long)c);
+            atomicMin(reinterpret_cast<unsigned long long *>(a.first), (unsigned long long)loc_first);
+        }
+    }
+}
+
+// Plain copy with the same tiling: the bandwidth ceiling for the repair.
+template <int R, bool NT>
+__global__ void __launch_bounds__(1024) copy_kernel(const uint16_t *in, uint16_t *out, int64_t lo, int64_t hi) {
+    constexpr int64_t T = kRowUnits * R;
+    const int lane = __lane_id();
+    const int64_t wg_waves = blockDim.x >> 6;
+    const int64_t nwaves = (int64_t)gridDim.x * wg_waves;
+    const int64_t wave = (int64_t)blockIdx.x * wg_waves + (threadIdx.x >> 6);
+    if (hi <= lo)
+        return;
+    const int64_t t0 = lo / T, t1 = (hi + T - 1) / T;
+    const int64_t per = (t1 - t0 + nwaves - 1) / nwaves;
+    const int64_t tb = t0 + wave * per;
+    const int64_t te = min(tb + per, t1);
+    for (int64_t t = tb; t < te; ++t) {
+        const int64_t tl = t * T;
+        const bool interior = tl >= lo && tl + T <= hi;
+        u32x4 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t u0 = tl + ((int64_t)r * 64 + lane) * 8;
+            v[r] = interior ? ld16<NT>(in + u0) : ld_partial(in, u0, lo, hi);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t u0 = tl + ((int64_t)r * 64 + lane) * 8;
+            if (interior)
+                st16<NT>(out + u0, v[r]);
+            else
+                st_partial(out, u0, lo, hi, v[r], 0x8080808080808080ull);
+        }
+    }
+}
+
+template <typename T>
+__global__ void fill_kernel(T *p, T v, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        p[i] = v;
+}
+
+__global__ void validate_kernel(const int64_t *off, int64_t nstr, int64_t buf_units, int32_t *bad) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= nstr; i += stride) {
+        const int64_t o = off[i];
+        bool ok = o >= 0 && o <= buf_units;
+        if (i < nstr)
+            ok = ok && off[i + 1] >= o;
+        if (!ok)
+            *bad = 1;
+    }
+}
+
+template <typename T>
+hipError_t fill(T *p, T v, int64_t n, hipStream_t s) {
+    if (n <= 0)
+        return hipSuccess;
+    const int64_t blocks = min((n + 255) / 256, (int64_t)4096);
+    hipLaunchKernelGGL(fill_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+template <int OP, bool BATCH, int R, bool NT>
+hipError_t launch_r(const LaunchShape &sh, const KernelArgs &a, hipStream_t s) {
+    const dim3 grid((unsigned)sh.grid), block((unsigned)(64 * sh.wg_waves));
+    if (OP == kOpTo && a.scalar_store)
+        hipLaunchKernelGGL((wf_kernel<OP, BATCH, R, NT, true>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((wf_kernel<OP, BATCH, R, NT, false>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+template <int OP, bool BATCH>
+hipError_t launch_ob(const LaunchShape &sh, const KernelArgs &a, hipStream_t s) {
+    const bool nt = sh.nontemporal != 0;
+    switch (sh.rows) {
+    case 1: return nt ? launch_r<OP, BATCH, 1, true>(sh, a, s) : launch_r<OP, BATCH, 1, false>(sh, a, s);
+    case 2: return nt ? launch_r<OP, BATCH, 2, true>(sh, a, s) : launch_r<OP, BATCH, 2, false>(sh, a, s);
+    case 4: return nt ? launch_r<OP, BATCH, 4, true>(sh, a, s) : launch_r<OP, BATCH, 4, false>(sh, a, s);
+    case 8: return nt ? launch_r<OP, BATCH, 8, true>(sh, a, s) : launch_r<OP, BATCH, 8, false>(sh, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <bool BATCH>
+hipError_t launch_b(int op, const LaunchShape &sh, const KernelArgs &a, hipStream_t s) {
+    switch (op) {
+    case kOpIs: return launch_ob<kOpIs, BATCH>(sh, a, s);
+    case kOpTo: return launch_ob<kOpTo, BATCH>(sh, a, s);
+    case kOpToInplace: return launch_ob<kOpToInplace, BATCH>(sh, a, s);
+    case kOpLocate: return launch_ob<kOpLocate, BATCH>(sh, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int R>
+hipError_t launch_copy_r(const uint16_t *in, uint16_t *out, int64_t lo, int64_t hi, const LaunchShape &sh,
+                         hipStream_t s) {
+    const dim3 grid((unsigned)sh.grid), block((unsigned)(64 * sh.wg_waves));
+    if (sh.nontemporal)
+        hipLaunchKernelGGL((copy_kernel<R, true>), grid, block, 0, s, in, out, lo, hi);
+    else
+        hipLaunchKernelGGL((copy_kernel<R, false>), grid, block, 0, s, in, out, lo, hi);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_main(int op, bool batch, const LaunchShape &shape, const KernelArgs &a, hipStream_t stream) {
+    return batch ? launch_b<true>(op, shape, a, stream) : launch_b<false>(op, shape, a, stream);
+}
+
+hipError_t launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s) { return fill<uint8_t>(p, v, n, s); }
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) { return fill<int32_t>(p, v, n, s); }
+hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s) { return fill<int64_t>(p, v, n, s); }
+
+hipError_t launch_copy(const uint16_t *in, uint16_t *out, int64_t lo, int64_t hi, const LaunchShape &shape,
+                       hipStream_t s) {
+    switch (shape.rows) {
+    case 1: return launch_copy_r<1>(in, out, lo, hi, shape, s);
+    case 2: return launch_copy_r<2>(in, out, lo, hi, shape, s);
+    case 4: return launch_copy_r<4>(in, out, lo, hi, shape, s);
+    case 8: return launch_copy_r<8>(in, out, lo, hi, shape, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_validate(const int64_t *offsets, int64_t nstr, int64_t buf_units, int32_t *bad, hipStream_t s) {
+    const int64_t blocks = min((nstr + 1 + 255) / 256, (int64_t)4096);
+    hipLaunchKernelGGL(validate_kernel, dim3((unsigned)blocks), dim3(256), 0, s, offsets, nstr, buf_units, bad);
+    return hipGetLastError();
+}
+
+}  // namespace utf16wf

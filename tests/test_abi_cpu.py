@@ -1,0 +1,131 @@
+"""C-ABI tests that need no GPU: the library loads, exports every symbol the
+header declares, and rejects bad arguments before making any HIP call."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER_DIR = os.path.join(ROOT, "include")
+
+
+def _declared_functions():
+    names = []
+    for fn in sorted(os.listdir(HEADER_DIR)):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(HEADER_DIR, fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(utf16\w*)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2601_06349_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libutf16wf.so is not built (run __graft_entry__.build())")
+    return _lib.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared_functions()
+    assert len(names) >= 20, names
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in include/ but not exported"
+    from paper_2601_06349_amd import _lib
+    assert set(names) <= set(_lib.SIGNATURES), "binding is missing a declared function"
+
+
+def test_abi_version(L):
+    assert L.utf16wf_abi_version() == 1
+
+
+def _rc(L, name, *args):
+    return getattr(L, name)(*args)
+
+
+A = 0x10000  # a fake, never dereferenced, 16-byte aligned address
+
+
+def test_flat_argument_errors(L):
+    from paper_2601_06349_amd import EALIGN, EINVAL, EOVERLAP
+    assert _rc(L, "utf16_to_well_formed", A, A + 4096, -1, None) == EINVAL
+    assert _rc(L, "utf16_to_well_formed", None, A, 5, None) == EINVAL
+    assert _rc(L, "utf16_to_well_formed", A, None, 5, None) == EINVAL
+    assert _rc(L, "utf16_to_well_formed", A + 1, A + 4096, 5, None) == EALIGN
+    assert _rc(L, "utf16_to_well_formed", A, A + 4097, 5, None) == EALIGN
+    assert _rc(L, "utf16_to_well_formed", A, A + 2, 5, None) == EOVERLAP
+    assert _rc(L, "utf16_to_well_formed", A + 8, A, 5, None) == EOVERLAP
+    assert _rc(L, "utf16_to_well_formed", A, A, 0, None) == 0  # nothing to do
+    assert _rc(L, "utf16_to_well_formed_inplace", A + 1, 3, None) == EALIGN
+    assert _rc(L, "utf16_is_well_formed", A, 5, None, None) == EINVAL
+    assert _rc(L, "utf16_is_well_formed", A, 5, A + 4098, None) == EALIGN
+    assert _rc(L, "utf16_is_well_formed", A + 1, 5, A + 4096, None) == EALIGN
+    assert _rc(L, "utf16_is_well_formed", A, -2, A + 4096, None) == EINVAL
+    assert _rc(L, "utf16_locate_ill_formed", A, 5, A + 4096, A + 4100, None) == EALIGN
+    assert _rc(L, "utf16_locate_ill_formed", A, 5, None, A + 4104, None) == EINVAL
+    assert _rc(L, "utf16wf_copy_units", A, A + 4098, 4, None) == EALIGN
+    msg = L.utf16wf_last_error().decode()
+    assert "alignment" in msg or "aligned" in msg
+
+
+def test_batch_argument_errors(L):
+    from paper_2601_06349_amd import EALIGN, EINVAL
+    assert _rc(L, "utf16_to_well_formed_batch", A, A + 4096, A + 8192, -1, None) == EINVAL
+    assert _rc(L, "utf16_to_well_formed_batch", A, A + 4096, A + 8192, 0, None) == 0
+    assert _rc(L, "utf16_to_well_formed_batch", None, A + 4096, A + 8192, 3, None) == EINVAL
+    assert _rc(L, "utf16_to_well_formed_batch", A, A + 4096, None, 3, None) == EINVAL
+    assert _rc(L, "utf16_to_well_formed_batch", A, A + 4096, A + 8196, 3, None) == EALIGN
+    assert _rc(L, "utf16_to_well_formed_batch", A + 1, A + 4096, A + 8192, 3, None) == EALIGN
+    assert _rc(L, "utf16_is_well_formed_batch", A, A + 8192, 3, None, None) == EINVAL
+    assert _rc(L, "utf16_locate_ill_formed_batch", A, A + 8192, 3, None, A, None) == EINVAL
+    assert _rc(L, "utf16wf_batch", 9, A, A, A + 8192, 3, None, None, None, 0, None) == EINVAL
+    assert _rc(L, "utf16wf_batch", 1, A, A, A + 8192, 3, None, None, None, -5, None) == EINVAL
+    assert _rc(L, "utf16wf_validate_offsets", None, 3, 10, None) == EINVAL
+    assert _rc(L, "utf16wf_validate_offsets", A + 4, 3, 10, None) == EALIGN
+    assert _rc(L, "utf16wf_validate_offsets", A, -1, 10, None) == EINVAL
+
+
+def test_plan_argument_errors(L):
+    from paper_2601_06349_amd import EINVAL
+    h = ctypes.c_void_p()
+    assert _rc(L, "utf16wf_batch_plan_create", 1, A, A + 4096, A + 8192, 3, None, None, None) == EINVAL
+    assert _rc(L, "utf16wf_batch_plan_create", 7, A, A + 4096, A + 8192, 3, None, None, ctypes.byref(h)) == EINVAL
+    assert _rc(L, "utf16wf_batch_plan_create", 3, A, None, A + 8192, 3, None, None, ctypes.byref(h)) == EINVAL
+    assert _rc(L, "utf16wf_batch_plan_create", 0, A, None, A + 8192, 3, None, None, ctypes.byref(h)) == EINVAL
+    assert _rc(L, "utf16wf_batch_plan_launch", None, None) == EINVAL
+    assert _rc(L, "utf16wf_batch_plan_destroy", None) == 0
+
+
+def test_params_roundtrip(L):
+    import paper_2601_06349_amd as wf
+    wf.reset_params()
+    d = wf.get_params(wf.OP_TO, 0, 1 << 28)
+    assert d["rows"] in (1, 2, 4, 8) and 1 <= d["wg_waves"] <= 16
+    wf.set_params(wf.OP_TO, 0, 28, rows=8, wg_waves=2, grid_per_cu=3, nontemporal=1)
+    assert wf.get_params(wf.OP_TO, 0, (1 << 28) + 5) == {"rows": 8, "wg_waves": 2, "grid_per_cu": 3,
+                                                         "nontemporal": 1}
+    assert wf.get_params(wf.OP_TO, 0, 1 << 27) == wf.get_params(wf.OP_TO, 0, (1 << 27) + 1)
+    with pytest.raises(wf.Utf16wfError):
+        wf.set_params(wf.OP_TO, 0, 28, rows=3, wg_waves=2, grid_per_cu=3, nontemporal=0)
+    with pytest.raises(wf.Utf16wfError):
+        wf.set_params(wf.OP_TO, 0, 41, rows=4, wg_waves=2, grid_per_cu=3, nontemporal=0)
+    with pytest.raises(wf.Utf16wfError):
+        wf.set_params(wf.OP_TO, 2, 10, rows=4, wg_waves=2, grid_per_cu=3, nontemporal=0)
+    wf.reset_params()
+    assert wf.get_params(wf.OP_TO, 0, 1 << 28) == d
+
+
+def test_product_path_has_no_cpu_route():
+    """The package never imports the oracle and the binding has no fallback."""
+    pkg = os.path.join(ROOT, "paper_2601_06349_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "utf16_oracle" not in text and "liboracle" not in text, f

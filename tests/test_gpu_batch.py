@@ -1,0 +1,219 @@
+"""GPU parity of the ragged-batch entry points and batch plans against the
+CPU oracle (per-string repair), bit-exact."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2601_06349_amd import workloads as W
+from tests.gpu_util import assert_same, log, offsets_dev, to_dev, to_host, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+H, L, A = 0xD801, 0xDC02, 0x0041
+ROWS = (1, 2, 4, 8)
+
+
+@pytest.fixture(scope="module")
+def wf():
+    torch_mod()
+    import paper_2601_06349_amd as wf
+    wf.reset_params()
+    yield wf
+    wf.reset_params()
+
+
+def _force_rows(wf, rows, wg_waves=4, grid_per_cu=8, nt=0):
+    for op in (wf.OP_IS, wf.OP_TO, wf.OP_TO_INPLACE, wf.OP_LOCATE):
+        wf.set_params(op, 1, -1, rows=rows, wg_waves=wg_waves, grid_per_cu=grid_per_cu, nontemporal=nt)
+
+
+def _check_batch(wf, buf, off, phase_in=0, phase_out=0, what="", hint=0):
+    torch = torch_mod()
+    off = np.asarray(off, np.int64)
+    b = off.size - 1
+    sentinel = np.full(buf.size, 0x1234, np.uint16)
+    want = oracle.to_well_formed_batch(buf, off, out=sentinel)
+    want_ip = oracle.to_well_formed_batch(buf, off)
+    t_in, _ = to_dev(buf, phase_in, pad=8)
+    t_off = offsets_dev(off)
+    t_out, _ = to_dev(sentinel, phase_out, pad=8)
+    if hint:
+        wf.utf16wf_batch(wf.OP_TO, t_in, t_off, out=t_out, units_hint=hint)
+    else:
+        wf.utf16_to_well_formed_batch(t_in, t_off, out=t_out)
+    assert_same(to_host(t_out), want, f"batch oop {what} phase {phase_in}/{phase_out}")
+    t_ip, _ = to_dev(buf, phase_in, pad=8)
+    wf.utf16_to_well_formed_batch_inplace(t_ip, t_off)
+    assert_same(to_host(t_ip), want_ip, f"batch inplace {what}")
+    res = to_host(wf.utf16_is_well_formed_batch(t_in, t_off)).view(np.uint8)
+    want_res = oracle.is_well_formed_batch(buf, off)
+    assert np.array_equal(res, want_res), f"batch is {what}: {np.nonzero(res != want_res)[0][:10]}"
+    first, cnt = wf.utf16_locate_ill_formed_batch(t_in, t_off)
+    wf_first, wf_cnt = oracle.locate_batch(buf, off)
+    assert np.array_equal(first.cpu().numpy(), wf_first), f"batch first_bad {what}"
+    assert np.array_equal(cnt.cpu().numpy(), wf_cnt), f"batch count {what}"
+    torch.cuda.synchronize()
+    return b
+
+
+def _random_batch(rng, b, max_len, alphabet, pre=0, post=0):
+    lens = rng.integers(0, max_len + 1, size=b)
+    total = int(lens.sum()) + pre + post
+    buf = alphabet[rng.integers(0, alphabet.size, size=total)].astype(np.uint16)
+    off = np.concatenate([[pre], pre + np.cumsum(lens)]).astype(np.int64)
+    return buf, off
+
+
+@pytest.mark.parametrize("rows", ROWS)
+def test_random_batches(wf, rows):
+    _force_rows(wf, rows)
+    rng = np.random.default_rng(rows)
+    alphabet = np.array([A, 0x4E2D, H, L, 0xDBFF, 0xDFFF], np.uint16)
+    for i, (b, max_len) in enumerate([(1, 0), (1, 1), (3, 5), (40, 12), (300, 40), (1000, 3), (50, 3000),
+                                      (7, 9000)]):
+        buf, off = _random_batch(rng, b, max_len, alphabet, pre=i % 5, post=(3 * i) % 7)
+        _check_batch(wf, buf, off, what=f"rows={rows} b={b} max={max_len}")
+    wf.reset_params()
+
+
+def test_phases(wf):
+    rng = np.random.default_rng(42)
+    alphabet = np.array([A, H, L], np.uint16)
+    buf, off = _random_batch(rng, 500, 30, alphabet, pre=3, post=2)
+    for pi, po in [(0, 0), (1, 1), (7, 7), (0, 3), (5, 2), (4, 0)]:
+        _check_batch(wf, buf, off, pi, po, what="phases")
+
+
+def test_no_pairing_across_strings(wf):
+    """Every string ends in a high and the next starts with a low: a flat
+    repair of the concatenation would keep these pairs; the batch must not."""
+    rng = np.random.default_rng(1)
+    lens = rng.integers(2, 20, size=5000)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    buf = np.full(int(off[-1]), A, np.uint16)
+    buf[off[1:] - 1] = H
+    buf[off[:-1]] = L
+    flat = oracle.to_well_formed(buf)
+    per = oracle.to_well_formed_batch(buf, off)
+    assert not np.array_equal(flat, per)
+    _check_batch(wf, buf, off, what="adversarial ends")
+
+
+def test_tiny_and_empty_strings(wf):
+    """Thousands of one-unit strings per tile and long runs of empty strings
+    at one position (more than a wave's worth of offsets per scan step)."""
+    for rows in ROWS:
+        _force_rows(wf, rows)
+        buf = np.tile(np.array([H, L, A, L, H], np.uint16), 3000)
+        off = np.arange(buf.size + 1, dtype=np.int64)
+        _check_batch(wf, buf, off, what=f"unit strings rows={rows}")
+        lens = np.zeros(700, np.int64)
+        lens[::100] = 37
+        lens[350] = 5000
+        off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+        buf = W.mix(int(off[-1]), 0.05, 9)
+        _check_batch(wf, buf, off, what=f"empty runs rows={rows}")
+        off = np.zeros(300, np.int64)  # all strings empty
+        _check_batch(wf, np.zeros(10, np.uint16) + H, off, what="all empty")
+    wf.reset_params()
+
+
+def test_long_string_among_short(wf):
+    rng = np.random.default_rng(5)
+    lens = rng.integers(1, 50, size=2000)
+    lens[1000] = 3_000_017
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    buf = W.mix(int(off[-1]), 1e-3, 6)
+    _check_batch(wf, buf, off, what="long among short")
+    _check_batch(wf, buf, off, what="long among short, hinted", hint=int(off[-1]))
+
+
+def test_is_early_exit_long_bad_strings(wf):
+    """Long ill-formed strings whose later tiles are skipped once the first
+    error is known; every result must still be exact."""
+    lens = np.array([2_000_000, 5, 1_500_000, 1, 3_000_000], np.int64)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    buf = W.ascii_units(int(off[-1]), 3)
+    buf[10] = H  # string 0 bad at its start
+    buf[off[2] + 1_400_000] = L  # string 2 bad near its end
+    buf[off[4]] = L
+    for rows in ROWS:
+        _force_rows(wf, rows)
+        _check_batch(wf, buf, off, what=f"early exit rows={rows}")
+    wf.reset_params()
+
+
+def test_plans_replay(wf):
+    torch = torch_mod()
+    rng = np.random.default_rng(11)
+    buf, off = _random_batch(rng, 3000, 25, np.array([A, H, L], np.uint16))
+    t_in, _ = to_dev(buf)
+    t_off = offsets_dev(off)
+    t_out, _ = to_dev(np.zeros_like(buf))
+    res = torch.empty(off.size - 1, dtype=torch.uint8, device="cuda")
+    p_to = wf.BatchPlan(wf.OP_TO, t_in, t_off, out=t_out)
+    p_is = wf.BatchPlan(wf.OP_IS, t_in, t_off, results=res)
+    for rep in range(4):
+        cur = buf.copy()
+        cur[rng.integers(0, buf.size, size=50)] = H  # new content each replay
+        t_in.copy_(torch.from_numpy(cur.view(np.int16)))
+        t_out.zero_()
+        res.fill_(7)
+        p_to.launch()
+        p_is.launch()
+        torch.cuda.synchronize()
+        assert_same(to_host(t_out), oracle.to_well_formed_batch(cur, off), f"plan replay {rep}")
+        assert np.array_equal(res.cpu().numpy(), oracle.is_well_formed_batch(cur, off)), f"plan is {rep}"
+    p_to.close()
+    p_is.close()
+    # in-place plan
+    t_ip, _ = to_dev(buf)
+    p_ip = wf.BatchPlan(wf.OP_TO_INPLACE, t_ip, t_off)
+    p_ip.launch()
+    p_ip.launch()  # idempotent
+    torch.cuda.synchronize()
+    assert_same(to_host(t_ip), oracle.to_well_formed_batch(buf, off), "plan inplace")
+    p_ip.close()
+
+
+def test_validate_offsets(wf):
+    good = offsets_dev(np.array([0, 3, 3, 10], np.int64))
+    wf.utf16wf_validate_offsets(good, 10)
+    for bad, n in (([0, 3, 2, 10], 10), ([0, 3, 5, 11], 10), ([-1, 3, 5, 9], 10)):
+        with pytest.raises(wf.Utf16wfError) as e:
+            wf.utf16wf_validate_offsets(offsets_dev(np.array(bad, np.int64)), n)
+        assert e.value.code == wf.EOFFSETS
+
+
+def test_ragged_1m_full(wf):
+    """1,000,000 log-normal strings (about 98.6M units), default shape."""
+    log("generating ragged_1m")
+    buf, off = W.ragged_batch()
+    log(f"ragged_1m: {off.size - 1} strings, {off[-1]} units")
+    _check_batch(wf, buf, off, what="ragged_1m")
+
+
+def test_zipf_4096_full(wf):
+    """4096 Zipf(1.1) strings up to 2^24 units (about 1.6G units), default
+    shape: out of place, in place, is (early exit), locate."""
+    torch = torch_mod()
+    log("generating zipf_4096")
+    buf, off, kind = W.zipf_batch()
+    log(f"zipf_4096: {off[-1]} units, {int(kind.sum())} error strings")
+    t_in = torch.from_numpy(buf.view(np.int16)).to("cuda")
+    t_off = offsets_dev(off)
+    want = oracle.to_well_formed_batch(buf, off)
+    out = wf.utf16_to_well_formed_batch(t_in, t_off, out=torch.empty_like(t_in))
+    assert_same(to_host(out), want, "zipf oop")
+    del out
+    res = wf.utf16_is_well_formed_batch(t_in, t_off).cpu().numpy()
+    assert np.array_equal(res, oracle.is_well_formed_batch(buf, off))
+    first, cnt = wf.utf16_locate_ill_formed_batch(t_in, t_off)
+    of, oc = oracle.locate_batch(buf, off)
+    assert np.array_equal(first.cpu().numpy(), of) and np.array_equal(cnt.cpu().numpy(), oc)
+    wf.utf16_to_well_formed_batch_inplace(t_in, t_off)
+    assert_same(to_host(t_in), want, "zipf inplace")
+    del t_in
+    torch.cuda.empty_cache()
