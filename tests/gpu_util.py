@@ -30,10 +30,10 @@ def to_dev(arr: np.ndarray, phase: int = 0, pad: int = 0):
     start = phase + pad
     # torch allocations are 256-byte aligned, so `start` units in gives phase
     view = base[start:start + n]
-    assert (view.data_ptr() - base.data_ptr()) == 2 * start
-    assert (base.data_ptr() & 15) == 0
-    assert (view.data_ptr() & 15) == (2 * phase) % 16
     if n:
+        assert (view.data_ptr() - base.data_ptr()) == 2 * start
+        assert (base.data_ptr() & 15) == 0
+        assert (view.data_ptr() & 15) == (2 * phase) % 16
         view.copy_(torch.from_numpy(arr.view(np.int16)))
     return view, base
 
