@@ -1,0 +1,309 @@
+"""Benchmark: UTF-16 toWellFormed throughput on one MI355X.
+
+One step = one pass of the repair over the single-buffer workload: five
+buffers of 268,435,456 uint16 units (512 MiB each) — pure ASCII, the
+character mix at lone-surrogate rates 0, 1e-6 and 1e-2, and all units uniform
+over the surrogate range — each repaired out of place by one launch. The
+inputs are resident in HBM before timing starts. ``value`` is GB/s of input
+(2 bytes per unit) over the whole job.
+
+The JSON line also carries
+  * ``roofline``: the repair kernel's algorithmic bytes (4 per unit: read and
+    write) divided by its mean launch time from HIP events on its stream,
+    against the 8 TB/s HBM peak; ``traffic`` comes from the rocprofv3 counter
+    summary under profiles/ when it was taken on the current kernel source;
+  * ``cpu_baseline``: the scalar CPU oracle timed on this host's cores over a
+    bounded sample of the same inputs;
+  * per-variant GB/s for copy, in place and isWellFormed, the copy ceiling,
+    the ragged batch in one launch against one launch per string, the
+    autotuned large-batch numbers and the serving loop's p50/p99 latency
+    (skip these with --no-extras).
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "toWellFormed GB/s input and % HBM peak; batched vs per-string; serve p99"
+PEAK_HBM_GBS = 8000.0
+N_UNITS = 1 << 28
+KERNEL_SRC = os.path.join(ROOT, "paper_2601_06349_amd", "csrc", "kernels.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "flat_to_single268M_pmc.md")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per launch from the committed counter summary, or None when
+    missing or taken on a different kernel source."""
+    try:
+        text = open(PMC_SUMMARY).read()
+    except OSError:
+        return None
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+class Timer:
+    """HIP events recorded on the stream the kernels are launched on."""
+
+    def __init__(self, torch, stream):
+        self.torch = torch
+        self.stream = stream
+        self.pairs = []
+
+    def run(self, fn):
+        a = self.torch.cuda.Event(enable_timing=True)
+        b = self.torch.cuda.Event(enable_timing=True)
+        a.record(self.stream)
+        fn()
+        b.record(self.stream)
+        self.pairs.append((a, b))
+
+    def times_ms(self):
+        self.torch.cuda.synchronize()
+        return [a.elapsed_time(b) for a, b in self.pairs]
+
+
+def median(xs):
+    xs = sorted(xs)
+    return xs[len(xs) // 2] if xs else float("nan")
+
+
+def time_fn(torch, stream, fn, reps=10, setup=None):
+    """Median and best event time (ms) of fn over reps, setup untimed."""
+    fn()
+    torch.cuda.synchronize()
+    t = Timer(torch, stream)
+    for _ in range(reps):
+        if setup:
+            setup()
+        t.run(fn)
+    ts = t.times_ms()
+    return median(ts), min(ts)
+
+
+def cpu_baseline(inputs, budget_s=12.0):
+    """The oracle as it stands (single-threaded scalar C) over the benchmark's
+    own inputs, whole buffers in order, until about budget_s of CPU work."""
+    import oracle
+    lib = oracle._load()
+    done_units, t0 = 0, time.perf_counter()
+    passes = 0
+    out = np.empty(inputs[0].size, dtype=np.uint16)
+    while True:
+        for s in inputs:
+            lib.wf_to_seq(s.ctypes.data, out.ctypes.data, s.size)
+            done_units += s.size
+            if time.perf_counter() - t0 >= budget_s:
+                break
+        passes += 1
+        if time.perf_counter() - t0 >= budget_s or passes >= 4:
+            break
+    el = time.perf_counter() - t0
+    return {
+        "value": round(2.0 * done_units / el / 1e9, 3),
+        "unit": "GB/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{done_units} units of the benchmark's own five buffers, repaired out of place by the "
+                  f"single-threaded scalar oracle (gcc -O2 -fno-tree-vectorize) in {el:.1f} s",
+    }
+
+
+def per_string_vs_batched(torch, wf, stream, sample=20000):
+    """Ragged batch of 1,000,000 log-normal strings: one persistent launch
+    against one flat launch per string (timed on a prefix sample)."""
+    from paper_2601_06349_amd import workloads as W
+    buf, off = W.ragged_batch()
+    n = int(off[-1])
+    t_in = torch.from_numpy(buf.view(np.int16)).cuda()
+    t_off = torch.from_numpy(off).cuda()
+    t_out = torch.empty_like(t_in)
+    med, best = time_fn(torch, stream, lambda: wf.utf16wf_batch(wf.OP_TO, t_in, t_off, out=t_out,
+                                                                units_hint=n), reps=20)
+    plan = wf.BatchPlan(wf.OP_TO, t_in, t_off, out=t_out)
+    med_plan, _ = time_fn(torch, stream, plan.launch, reps=20)
+    plan.close()
+    L = wf.lib()
+    base_in, base_out, sh = t_in.data_ptr(), t_out.data_ptr(), stream.cuda_stream
+    k = min(sample, off.size - 1)
+    starts, lens = off[:k], off[1:k + 1] - off[:k]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, ln in zip(starts.tolist(), lens.tolist()):
+        L.utf16_to_well_formed(base_in + 2 * a, base_out + 2 * a, ln, sh)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    per_string_est_ms = el * 1e3 * (off.size - 1) / k
+    return {
+        "workload": "1,000,000 strings, log-normal lengths (median 32, sigma 1.5), "
+                    f"{n} units, mix at 1e-3 plus forced edge surrogates",
+        "batched_ms": round(med, 4),
+        "batched_plan_ms": round(med_plan, 4),
+        "batched_input_GBps": round(2 * n / (med * 1e-3) / 1e9, 1),
+        "batched_pct_hbm": round(100 * (4 * n + 8 * off.size) / (med * 1e-3) / 1e9 / PEAK_HBM_GBS, 1),
+        "per_string_ms_estimated": round(per_string_est_ms, 1),
+        "per_string_sample": f"first {k} strings, one launch each, scaled to all strings",
+        "speedup": round(per_string_est_ms / med, 1),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-extras", action="store_true", help="only the timed steps, roofline and CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for rocprofv3: the steps plus one copy-kernel launch, no extras")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2601_06349_amd as wf
+    from paper_2601_06349_amd import tune
+    from paper_2601_06349_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    wf.lib()  # fails loudly when the HIP library is missing
+    tuned = tune.apply_cache()
+    stream = torch.cuda.current_stream()
+
+    log("generating inputs")
+    host_inputs = [W.single_buffer(v) for v in W.SINGLE_VARIANTS]
+    d_in = [torch.from_numpy(s.view(np.int16)).cuda() for s in host_inputs]
+    d_out = [torch.empty_like(x) for x in d_in]
+    torch.cuda.synchronize()
+
+    launches = Timer(torch, stream)
+
+    def step(timer=None):
+        for x, y in zip(d_in, d_out):
+            if timer is None:
+                wf.utf16_to_well_formed(x, y)
+            else:
+                timer.run(lambda x=x, y=y: wf.utf16_to_well_formed(x, y))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(launches)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    if args.profile:
+        wf.utf16wf_copy_units(d_in[0], d_out[0])
+        torch.cuda.synchronize()
+
+    launch_ms = launches.times_ms()
+    mean_launch_s = sum(launch_ms) / len(launch_ms) * 1e-3
+    in_bytes = 2 * N_UNITS * len(d_in) * args.steps
+    value = in_bytes / el / 1e9
+    achieved = 4 * N_UNITS / mean_launch_s / 1e9
+    traffic = read_traffic()
+    per_variant = {}
+    for i, v in enumerate(W.SINGLE_VARIANTS):
+        ts = launch_ms[i::len(d_in)]
+        per_variant[v] = round(2 * N_UNITS / (median(ts) * 1e-3) / 1e9, 1)
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(el * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16",
+        "data": "synthetic",
+        "config": {
+            "workload": "single buffer of 268,435,456 uint16 units (512 MiB) in five seeded variants "
+                        "(ascii, mix r=0, mix r=1e-6, mix r=1e-2, all surrogates); one step = "
+                        "out-of-place toWellFormed of all five",
+            "units_per_buffer": N_UNITS,
+            "buffers": len(d_in),
+            "launch_params": wf.get_params(wf.OP_TO, 0, N_UNITS),
+            "tuning_cache": tuned,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            "kernel": "wf_kernel<OP_TO, flat> (out-of-place repair)",
+            "algorithmic_bytes_per_launch": 4 * N_UNITS,
+            "mean_launch_us": round(mean_launch_s * 1e6, 2),
+        },
+        "per_variant_input_GBps": per_variant,
+    }
+
+    if not args.no_cpu and not args.profile:
+        log("cpu baseline")
+        result["cpu_baseline"] = cpu_baseline(host_inputs)
+
+    if not args.no_extras and not args.profile:
+        log("extras: in place, isWellFormed, copy ceiling")
+        ex = {}
+        inplace, isw = {}, {}
+        res = torch.empty(1, dtype=torch.int32, device="cuda")
+        scratch = torch.empty_like(d_in[0])
+        for i, v in enumerate(W.SINGLE_VARIANTS):
+            med, _ = time_fn(torch, stream, lambda: wf.utf16_to_well_formed_inplace(scratch), reps=10,
+                             setup=lambda: scratch.copy_(d_in[i]))
+            inplace[v] = round(2 * N_UNITS / (med * 1e-3) / 1e9, 1)
+            med, _ = time_fn(torch, stream, lambda: wf.utf16_is_well_formed(d_in[i], res), reps=10)
+            isw[v] = round(2 * N_UNITS / (med * 1e-3) / 1e9, 1)
+        ex["inplace_input_GBps"] = inplace
+        ex["is_well_formed_input_GBps"] = isw
+        med, _ = time_fn(torch, stream, lambda: wf.utf16wf_copy_units(d_in[0], d_out[0]), reps=20)
+        med_t, _ = time_fn(torch, stream, lambda: d_out[0].copy_(d_in[0]), reps=20)
+        ex["copy_ceiling"] = {"library_copy_GBps_rw": round(4 * N_UNITS / (med * 1e-3) / 1e9, 1),
+                              "torch_copy_GBps_rw": round(4 * N_UNITS / (med_t * 1e-3) / 1e9, 1)}
+        del scratch
+        log("extras: batched vs per-string")
+        ex["ragged_batch"] = per_string_vs_batched(torch, wf, stream)
+        result["extras"] = ex
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()
