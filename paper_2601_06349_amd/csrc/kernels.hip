@@ -270,10 +270,20 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
     uint64_t loc_first = ~0ull;
     uint32_t loc_count = 0;
 
+    // flat OP_IS early exit: the result word drops to 0 once any wave has
+    // seen a mismatch. The first poll waits (a wave that starts late skips
+    // all its loads); later polls are issued with a tile's loads and read at
+    // the next tile, so they add no latency.
+    int32_t poll = 1;
+    if constexpr (OP == kOpIs && !BATCH) {
+        if (__hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+            return;
+    }
+
     for (int64_t t = tb; t < te; ++t) {
         const int64_t tl = t * T, th = tl + T;
         if constexpr (OP == kOpIs && !BATCH) {
-            if (__hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+            if (poll == 0)
                 return;
         }
         const bool interior = tl >= lo && th <= hi;
@@ -297,6 +307,8 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
             else
                 v[r] = ld_partial(in, u0, lo, hi);
         }
+        if constexpr (OP == kOpIs && !BATCH)
+            poll = __hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if constexpr (BATCH && OP != kOpIs) {
             ts = scan_starts<R>(off, a.nstr, shift, cursor, tl, th, bm, lane);
             cursor = ts.knext;
@@ -354,18 +366,31 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
                 else
                     st_partial(out, u0, lo, hi, o, 0x8080808080808080ull);
             } else if constexpr (OP == kOpToInplace) {
-                if (lane_bad) {
-                    const u32x4 o = repair(v[r], badA, badB);
-                    if (interior)
-                        st16<NT>(out + u0, o);
-                    else
-                        st_partial(out, u0, lo, hi, o, bad64);
+                // Inside the buffer, the eight lanes of a 128-byte line store
+                // together when any of them changed, so memory sees whole-line
+                // writes rather than partial ones; unchanged lanes write back
+                // the values they read, which no other wave writes.
+                if (interior) {
+                    if ((wave_bad >> (lane & ~7)) & 0xFFull)
+                        st16<NT>(out + u0, lane_bad ? repair(v[r], badA, badB) : v[r]);
+                } else if (lane_bad) {
+                    st_partial(out, u0, lo, hi, repair(v[r], badA, badB), bad64);
                 }
             } else if constexpr (OP == kOpIs) {
                 if constexpr (!BATCH) {
                     if (wave_bad) {
-                        if (lane == 0)
-                            __hip_atomic_store(a.flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        // Every wave that sees a mismatch clears the result,
+                        // but only one in sixteen does so with a device-
+                        // coherent store (which other waves' polls observe);
+                        // the rest write through their cache, so thousands of
+                        // waves do not queue on one memory location.
+                        if (lane == 0 &&
+                            __hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                            if ((wave & 15) == 0)
+                                __hip_atomic_store(a.flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            else
+                                __hip_atomic_store(a.flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
                         return;
                     }
                 } else {
