@@ -1,0 +1,86 @@
+/*
+ * utf16wf serving loop: continuous batching of UTF-16 repair requests on one
+ * GPU. Not part of the paper (whose routine is a library call, Sec. 3); it
+ * drives the ragged-batch entry of utf16wf.h, whose per-string semantics are
+ * those of Sec. 1 and Sec. 3.1 applied to each request alone.
+ *
+ * Requests arrive on a schedule (arrival times relative to the start of the
+ * run). Each admitted request is copied from its device-resident payload into
+ * a packed batch inside one device arena, repaired (or checked) there by one
+ * batch launch, and, if the request names a destination, copied out. A
+ * request is admitted when the arena has room for it (the HBM budget) and a
+ * stream slot is free; batches on different slots run concurrently, and
+ * requests that arrive while batches are on the GPU join the next batch as
+ * soon as a slot and memory free up. Requests are admitted in arrival order
+ * (no reordering).
+ *
+ * Conventions as in utf16wf.h: device pointers, return UTF16WF_OK or a
+ * negative status, utf16wf_last_error() for the message.
+ */
+#ifndef UTF16WF_SERVE_H
+#define UTF16WF_SERVE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t num_streams;        /* batches in flight at once, 1..16 */
+    int32_t op;                 /* UTF16WF_OP_TO (repair) or UTF16WF_OP_IS (check) */
+    int64_t arena_bytes;        /* HBM budget: one device arena of this size */
+    int64_t max_batch_requests; /* at most this many requests per batch (>= 1) */
+    int64_t max_batch_units;    /* a batch stops growing past this many units (>= 1) */
+    int64_t timeout_ns;         /* a request still waiting this long after its
+                                   arrival is dropped (0 = never) */
+} utf16wf_serve_config;
+
+typedef struct {
+    int64_t arrival_ns;  /* scheduled arrival, non-decreasing over the array */
+    const uint16_t *src; /* device payload (any 2-byte alignment) */
+    int64_t length;      /* units, >= 0 */
+    uint16_t *dst;       /* device destination for the repaired units, or NULL */
+} utf16wf_serve_request;
+
+typedef struct {
+    int64_t launch_ns;   /* when its batch was launched (-1 if never) */
+    int64_t done_ns;     /* when the host saw its batch complete (-1 if never) */
+    int32_t status;      /* 0 done; UTF16WF_ERANGE larger than the arena;
+                            UTF16WF_EHIP launch failure; 1 timed out */
+    int32_t batch;       /* batch index (-1 if never launched) */
+    int32_t slot;        /* stream slot of its batch */
+    int32_t well_formed; /* UTF16WF_OP_IS: 1 / 0; otherwise -1 */
+} utf16wf_serve_outcome;
+
+typedef struct {
+    int64_t batches;
+    int64_t completed;
+    int64_t rejected;          /* larger than the whole arena */
+    int64_t timed_out;
+    int64_t failed;            /* batch launch failed */
+    int64_t max_inflight;      /* most batches in flight at once */
+    int64_t max_queue;         /* most requests waiting for admission */
+    int64_t arena_peak_bytes;  /* most arena bytes in use at once */
+    int64_t wall_ns;           /* from start to the last completion */
+} utf16wf_serve_stats;
+
+/* Runs the loop on the current device until every request is completed,
+ * rejected or timed out. Allocates the arena and per-slot buffers at the
+ * start and frees them at the end. Outcomes has n entries. Synchronous. */
+int utf16wf_serve_run(const utf16wf_serve_config *cfg, const utf16wf_serve_request *reqs, int64_t n,
+                      utf16wf_serve_outcome *outcomes, utf16wf_serve_stats *stats);
+
+/* The same scheduler with a simulated executor and a virtual clock, no GPU:
+ * a batch of U units completes lat_base_ns + lat_ns_per_unit * U after its
+ * launch; if fail_every > 0, every fail_every-th batch fails at launch.
+ * For capacity planning and for testing the scheduler on a CPU. */
+int utf16wf_serve_simulate(const utf16wf_serve_config *cfg, const int64_t *arrival_ns, const int64_t *lengths,
+                           int64_t n, int64_t lat_base_ns, double lat_ns_per_unit, int64_t fail_every,
+                           utf16wf_serve_outcome *outcomes, utf16wf_serve_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UTF16WF_SERVE_H */

@@ -73,6 +73,8 @@ SIGNATURES = {
     "utf16wf_reset_params": (_INT, []),
     "utf16wf_copy_units": (_INT, [_P, _P, _I64, _P]),
     "utf16wf_device_cus": (_INT, []),
+    "utf16wf_serve_run": (_INT, [_P, _P, _I64, _P, _P]),
+    "utf16wf_serve_simulate": (_INT, [_P, _P, _P, _I64, _I64, ctypes.c_double, _I64, _P, _P]),
     "utf16wf_last_error": (ctypes.c_char_p, []),
     "utf16wf_abi_version": (_INT, []),
 }

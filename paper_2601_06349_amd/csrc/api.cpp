@@ -287,6 +287,18 @@ int batch_call(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets
     return UTF16WF_OK;
 }
 
+}  // namespace
+
+namespace utf16wf {
+// Error reporting shared with the serving loop (serve.cpp).
+int set_error(int code, const char *msg) {
+    g_err = msg;
+    return code;
+}
+}  // namespace utf16wf
+
+namespace {
+
 struct Plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;

@@ -48,6 +48,15 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t stream)
 hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t stream);
 hipError_t launch_copy(const uint16_t *in, uint16_t *out, int64_t lo, int64_t hi,
                        const LaunchShape &shape, hipStream_t stream);
+// One contiguous piece of a gather or scatter copy (at most kCopyChunkUnits).
+struct CopyChunk {
+    const uint16_t *src;
+    uint16_t *dst;
+    int64_t n;
+};
+constexpr int64_t kCopyChunkUnits = 16384;
+hipError_t launch_chunk_copy(const CopyChunk *chunks, int64_t nchunks, hipStream_t stream);
+
 hipError_t launch_validate(const int64_t *offsets, int64_t nstr, int64_t buf_units, int32_t *bad,
                            hipStream_t stream);
 

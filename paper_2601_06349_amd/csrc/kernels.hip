@@ -502,6 +502,29 @@ __global__ void validate_kernel(const int64_t *off, int64_t nstr, int64_t buf_un
     }
 }
 
+// Copies each chunk (one workgroup per chunk): 16-byte accesses when source
+// and destination share their alignment modulo 16, else unit by unit.
+__global__ void __launch_bounds__(256) chunk_copy_kernel(const CopyChunk *chunks) {
+    const CopyChunk c = chunks[blockIdx.x];
+    const int64_t n = c.n;
+    const uintptr_t sa = reinterpret_cast<uintptr_t>(c.src), da = reinterpret_cast<uintptr_t>(c.dst);
+    if (((sa ^ da) & 15u) == 0 && n >= 64) {
+        const int64_t head = min(n, (int64_t)(((16u - (da & 15u)) & 15u) >> 1));
+        if (threadIdx.x < head)
+            c.dst[threadIdx.x] = c.src[threadIdx.x];
+        const int64_t nv = (n - head) >> 3;
+        const u32x4 *s4 = reinterpret_cast<const u32x4 *>(c.src + head);
+        u32x4 *d4 = reinterpret_cast<u32x4 *>(c.dst + head);
+        for (int64_t i = threadIdx.x; i < nv; i += blockDim.x)
+            d4[i] = s4[i];
+        for (int64_t i = head + nv * 8 + threadIdx.x; i < n; i += blockDim.x)
+            c.dst[i] = c.src[i];
+    } else {
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+            c.dst[i] = c.src[i];
+    }
+}
+
 template <typename T>
 hipError_t fill(T *p, T v, int64_t n, hipStream_t s) {
     if (n <= 0)
@@ -574,6 +597,13 @@ hipError_t launch_copy(const uint16_t *in, uint16_t *out, int64_t lo, int64_t hi
     case 8: return launch_copy_r<8>(in, out, lo, hi, shape, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_chunk_copy(const CopyChunk *chunks, int64_t nchunks, hipStream_t s) {
+    if (nchunks <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(chunk_copy_kernel, dim3((unsigned)nchunks), dim3(256), 0, s, chunks);
+    return hipGetLastError();
 }
 
 hipError_t launch_validate(const int64_t *offsets, int64_t nstr, int64_t buf_units, int32_t *bad, hipStream_t s) {

@@ -1,0 +1,302 @@
+// Serving loop on the GPU (include/utf16wf_serve.h): the scheduler of
+// serve_core.h driven by a HIP executor, and the same scheduler driven by a
+// simulated executor with a virtual clock.
+//
+// HIP executor, per batch on its slot's stream (default priority):
+//   1. offsets of the packed batch (H2D from pinned host memory, into the
+//      batch's arena region) and the gather descriptors (H2D);
+//   2. gather: each request's payload is copied into the packed input;
+//   3. one batch launch (utf16wf_batch) repairs into the packed output, or
+//      checks into per-string results;
+//   4. scatter to the requests' destinations (if any), result bytes D2H;
+//   5. an event; the loop polls it and then frees the region.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/utf16wf.h"
+#include "../../include/utf16wf_serve.h"
+#include "kernels.h"
+#include "serve_core.h"
+
+using namespace utf16wf;
+using namespace utf16wf::serve;
+
+namespace utf16wf {
+int set_error(int code, const char *msg);
+}
+
+namespace {
+
+int check_config(const utf16wf_serve_config *c, int64_t n) {
+    if (!c)
+        return set_error(UTF16WF_EINVAL, "null config");
+    if (n < 0)
+        return set_error(UTF16WF_EINVAL, "n < 0");
+    if (c->num_streams < 1 || c->num_streams > 16)
+        return set_error(UTF16WF_EINVAL, "num_streams must be 1..16");
+    if (c->op != UTF16WF_OP_TO && c->op != UTF16WF_OP_IS)
+        return set_error(UTF16WF_EINVAL, "op must be UTF16WF_OP_TO or UTF16WF_OP_IS");
+    if (c->arena_bytes < 256 || c->max_batch_requests < 1 || c->max_batch_units < 1 || c->timeout_ns < 0)
+        return set_error(UTF16WF_EINVAL, "bad arena / batch limits / timeout");
+    return UTF16WF_OK;
+}
+
+// ------------------------------------------------------------ HIP executor
+
+class HipExec {
+  public:
+    HipExec(const utf16wf_serve_config &cfg, const utf16wf_serve_request *reqs, int64_t n)
+        : cfg_(cfg), reqs_(reqs), n_(n) {}
+
+    int init() {
+        int64_t max_len = 0;
+        for (int64_t i = 0; i < n_; ++i)
+            max_len = std::max(max_len, reqs_[i].length);
+        const int64_t cap_units = std::max(cfg_.max_batch_units, max_len);
+        const int64_t cap_req = std::min<int64_t>(cfg_.max_batch_requests, std::max<int64_t>(n_, 1));
+        max_chunks_ = cap_units / kCopyChunkUnits + cap_req + 1;
+        max_req_ = cap_req;
+        hipError_t e = hipMalloc(&arena_, (size_t)cfg_.arena_bytes);
+        if (e != hipSuccess)
+            return fail(e, "hipMalloc(arena)");
+        const int slots = cfg_.num_streams;
+        slot_.resize(slots);
+        for (int s = 0; s < slots; ++s) {
+            Slot &sl = slot_[s];
+            if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess)
+                return fail(e, "hipStreamCreateWithFlags");
+            if ((e = hipEventCreateWithFlags(&sl.event, hipEventDisableTiming)) != hipSuccess)
+                return fail(e, "hipEventCreateWithFlags");
+            if ((e = hipHostMalloc((void **)&sl.h_off, 8 * (max_req_ + 1), 0)) != hipSuccess ||
+                (e = hipHostMalloc((void **)&sl.h_chunks, 2 * sizeof(CopyChunk) * max_chunks_, 0)) != hipSuccess ||
+                (e = hipHostMalloc((void **)&sl.h_res, max_req_ + 1, 0)) != hipSuccess)
+                return fail(e, "hipHostMalloc");
+            if ((e = hipMalloc((void **)&sl.d_chunks, 2 * sizeof(CopyChunk) * max_chunks_)) != hipSuccess)
+                return fail(e, "hipMalloc(chunks)");
+        }
+        t0_ = std::chrono::steady_clock::now();
+        return UTF16WF_OK;
+    }
+
+    ~HipExec() {
+        for (Slot &sl : slot_) {
+            if (sl.stream)
+                (void)hipStreamSynchronize(sl.stream);
+        }
+        for (Slot &sl : slot_) {
+            if (sl.event)
+                (void)hipEventDestroy(sl.event);
+            if (sl.stream)
+                (void)hipStreamDestroy(sl.stream);
+            if (sl.h_off)
+                (void)hipHostFree(sl.h_off);
+            if (sl.h_chunks)
+                (void)hipHostFree(sl.h_chunks);
+            if (sl.h_res)
+                (void)hipHostFree(sl.h_res);
+            if (sl.d_chunks)
+                (void)hipFree(sl.d_chunks);
+        }
+        if (arena_)
+            (void)hipFree(arena_);
+    }
+
+    int64_t now() const {
+        return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now() - t0_).count();
+    }
+
+    int launch(Batch &b) {
+        Slot &sl = slot_[b.slot];
+        uint8_t *base = static_cast<uint8_t *>(arena_) + b.region;
+        uint16_t *d_in = reinterpret_cast<uint16_t *>(base + b.lay.in_off);
+        uint16_t *d_out = reinterpret_cast<uint16_t *>(base + b.lay.out_off);
+        int64_t *d_offs = reinterpret_cast<int64_t *>(base + b.lay.offsets_off);
+        uint8_t *d_res = base + b.lay.results_off;
+        const int64_t nb = (int64_t)b.reqs.size();
+        int64_t g = 0, sc = 0, pos = 0;
+        CopyChunk *gat = sl.h_chunks, *sca = sl.h_chunks + max_chunks_;
+        sl.h_off[0] = 0;
+        for (int64_t i = 0; i < nb; ++i) {
+            const utf16wf_serve_request &r = reqs_[b.reqs[i]];
+            for (int64_t c = 0; c < r.length; c += kCopyChunkUnits) {
+                const int64_t len = std::min(kCopyChunkUnits, r.length - c);
+                gat[g++] = CopyChunk{r.src + c, d_in + pos + c, len};
+                if (r.dst && cfg_.op == UTF16WF_OP_TO)
+                    sca[sc++] = CopyChunk{d_out + pos + c, r.dst + c, len};
+            }
+            pos += r.length;
+            sl.h_off[i + 1] = pos;
+        }
+        hipStream_t st = sl.stream;
+        hipError_t e;
+        if ((e = hipMemcpyAsync(d_offs, sl.h_off, 8 * (nb + 1), hipMemcpyHostToDevice, st)) != hipSuccess)
+            return fail(e, "copy offsets");
+        if (g > 0 && (e = hipMemcpyAsync(sl.d_chunks, gat, sizeof(CopyChunk) * g, hipMemcpyHostToDevice, st)) !=
+                         hipSuccess)
+            return fail(e, "copy gather descriptors");
+        if (sc > 0 && (e = hipMemcpyAsync(sl.d_chunks + max_chunks_, sca, sizeof(CopyChunk) * sc,
+                                          hipMemcpyHostToDevice, st)) != hipSuccess)
+            return fail(e, "copy scatter descriptors");
+        if ((e = launch_chunk_copy(sl.d_chunks, g, st)) != hipSuccess)
+            return fail(e, "gather");
+        int rc;
+        if (cfg_.op == UTF16WF_OP_TO)
+            rc = utf16wf_batch(UTF16WF_OP_TO, d_in, d_out, d_offs, nb, nullptr, nullptr, nullptr, pos, st);
+        else
+            rc = utf16wf_batch(UTF16WF_OP_IS, d_in, nullptr, d_offs, nb, d_res, nullptr, nullptr, pos, st);
+        if (rc != UTF16WF_OK)
+            return rc;
+        if (sc > 0 && (e = launch_chunk_copy(sl.d_chunks + max_chunks_, sc, st)) != hipSuccess)
+            return fail(e, "scatter");
+        if (cfg_.op == UTF16WF_OP_IS &&
+            (e = hipMemcpyAsync(sl.h_res, d_res, nb, hipMemcpyDeviceToHost, st)) != hipSuccess)
+            return fail(e, "copy results");
+        if ((e = hipEventRecord(sl.event, st)) != hipSuccess)
+            return fail(e, "hipEventRecord");
+        return UTF16WF_OK;
+    }
+
+    int done(int slot) {
+        const hipError_t e = hipEventQuery(slot_[slot].event);
+        if (e == hipSuccess)
+            return 1;
+        if (e == hipErrorNotReady)
+            return 0;
+        fail(e, "hipEventQuery");
+        return -1;
+    }
+
+    void finish(const Batch &b, utf16wf_serve_outcome *out) {
+        if (cfg_.op != UTF16WF_OP_IS)
+            return;
+        const Slot &sl = slot_[b.slot];
+        for (size_t i = 0; i < b.reqs.size(); ++i)
+            out[b.reqs[i]].well_formed = sl.h_res[i];
+    }
+
+    void idle(int64_t next_arrival, bool any_busy) {
+        if (any_busy) {
+            std::this_thread::yield();
+            return;
+        }
+        if (next_arrival < 0)
+            return;
+        const int64_t wait = next_arrival - now();
+        if (wait > 200000)
+            std::this_thread::sleep_for(std::chrono::nanoseconds(wait - 100000));
+    }
+
+  private:
+    struct Slot {
+        hipStream_t stream = nullptr;
+        hipEvent_t event = nullptr;
+        int64_t *h_off = nullptr;
+        CopyChunk *h_chunks = nullptr;
+        uint8_t *h_res = nullptr;
+        CopyChunk *d_chunks = nullptr;
+    };
+    int fail(hipError_t e, const char *where) {
+        char buf[256];
+        snprintf(buf, sizeof buf, "serve: %s: %s", where, hipGetErrorString(e));
+        return set_error(UTF16WF_EHIP, buf);
+    }
+
+    utf16wf_serve_config cfg_;
+    const utf16wf_serve_request *reqs_;
+    int64_t n_;
+    int64_t max_chunks_ = 0, max_req_ = 0;
+    void *arena_ = nullptr;
+    std::vector<Slot> slot_;
+    std::chrono::steady_clock::time_point t0_;
+};
+
+// ------------------------------------------------------ simulated executor
+
+class SimExec {
+  public:
+    SimExec(int slots, int64_t base, double per_unit, int64_t fail_every)
+        : done_at_(slots, 0), base_(base), per_unit_(per_unit), fail_every_(fail_every) {}
+    int64_t now() const { return t_; }
+    int launch(Batch &b) {
+        ++launches_;
+        if (fail_every_ > 0 && launches_ % fail_every_ == 0)
+            return set_error(UTF16WF_EHIP, "simulated launch failure");
+        done_at_[b.slot] = t_ + base_ + (int64_t)(per_unit_ * (double)b.units);
+        return UTF16WF_OK;
+    }
+    int done(int slot) { return t_ >= done_at_[slot] ? 1 : 0; }
+    void finish(const Batch &, utf16wf_serve_outcome *) {}
+    void idle(int64_t next_arrival, bool any_busy) {
+        int64_t t = INT64_MAX;
+        if (next_arrival >= 0)
+            t = next_arrival;
+        if (any_busy)
+            for (int64_t d : done_at_)
+                if (d > t_)
+                    t = std::min(t, d);
+        t_ = (t == INT64_MAX) ? t_ + 1 : std::max(t, t_ + 1);
+    }
+
+  private:
+    std::vector<int64_t> done_at_;
+    int64_t base_;
+    double per_unit_;
+    int64_t fail_every_;
+    int64_t t_ = 0, launches_ = 0;
+};
+
+}  // namespace
+
+extern "C" {
+
+int utf16wf_serve_run(const utf16wf_serve_config *cfg, const utf16wf_serve_request *reqs, int64_t n,
+                      utf16wf_serve_outcome *outcomes, utf16wf_serve_stats *stats) {
+    int rc = check_config(cfg, n);
+    if (rc != UTF16WF_OK)
+        return rc;
+    if (n > 0 && (!reqs || !outcomes))
+        return set_error(UTF16WF_EINVAL, "null requests or outcomes");
+    std::vector<Request> rq((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        if (reqs[i].length < 0 || (reqs[i].length > 0 && !reqs[i].src))
+            return set_error(UTF16WF_EINVAL, "request with negative length or null payload");
+        if (reinterpret_cast<uintptr_t>(reqs[i].src) & 1u || reinterpret_cast<uintptr_t>(reqs[i].dst) & 1u)
+            return set_error(UTF16WF_EALIGN, "request pointer not 2-byte aligned");
+        if (i > 0 && reqs[i].arrival_ns < reqs[i - 1].arrival_ns)
+            return set_error(UTF16WF_EINVAL, "arrivals must be non-decreasing");
+        rq[(size_t)i] = Request{reqs[i].arrival_ns, reqs[i].length};
+    }
+    HipExec ex(*cfg, reqs, n);
+    if ((rc = ex.init()) != UTF16WF_OK)
+        return rc;
+    return run_loop(ex, *cfg, rq.data(), n, outcomes, stats);
+}
+
+int utf16wf_serve_simulate(const utf16wf_serve_config *cfg, const int64_t *arrival_ns, const int64_t *lengths,
+                           int64_t n, int64_t lat_base_ns, double lat_ns_per_unit, int64_t fail_every,
+                           utf16wf_serve_outcome *outcomes, utf16wf_serve_stats *stats) {
+    int rc = check_config(cfg, n);
+    if (rc != UTF16WF_OK)
+        return rc;
+    if (n > 0 && (!arrival_ns || !lengths || !outcomes))
+        return set_error(UTF16WF_EINVAL, "null arrays");
+    if (lat_base_ns < 0 || lat_ns_per_unit < 0 || fail_every < 0)
+        return set_error(UTF16WF_EINVAL, "negative latency model");
+    std::vector<Request> rq((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        if (lengths[i] < 0 || (i > 0 && arrival_ns[i] < arrival_ns[i - 1]))
+            return set_error(UTF16WF_EINVAL, "negative length or decreasing arrivals");
+        rq[(size_t)i] = Request{arrival_ns[i], lengths[i]};
+    }
+    SimExec ex(cfg->num_streams, lat_base_ns, lat_ns_per_unit, fail_every);
+    return run_loop(ex, *cfg, rq.data(), n, outcomes, stats);
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+"""Python front-end of the serving loop (include/utf16wf_serve.h).
+
+The loop itself is native (``utf16wf_serve_run``): arrivals replayed from a
+schedule, admission against an HBM arena, continuous batching over several
+streams, completion by event polling. This module builds request arrays,
+calls it, and summarises latencies (measured from each request's scheduled
+arrival, so a slow server cannot hide queueing delay).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from ._lib import OP_IS, OP_TO, check, lib
+
+REQUEST_DTYPE = np.dtype([("arrival_ns", "<i8"), ("src", "<u8"), ("length", "<i8"), ("dst", "<u8")])
+OUTCOME_DTYPE = np.dtype([("launch_ns", "<i8"), ("done_ns", "<i8"), ("status", "<i4"), ("batch", "<i4"),
+                          ("slot", "<i4"), ("well_formed", "<i4")])
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("num_streams", ctypes.c_int32), ("op", ctypes.c_int32), ("arena_bytes", ctypes.c_int64),
+                ("max_batch_requests", ctypes.c_int64), ("max_batch_units", ctypes.c_int64),
+                ("timeout_ns", ctypes.c_int64)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("batches", "completed", "rejected", "timed_out", "failed",
+                                               "max_inflight", "max_queue", "arena_peak_bytes", "wall_ns")]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+def make_config(num_streams=4, op=OP_TO, arena_bytes=64 << 30, max_batch_requests=4096,
+                max_batch_units=1 << 26, timeout_ns=0) -> ServeConfig:
+    return ServeConfig(num_streams, op, arena_bytes, max_batch_requests, max_batch_units, timeout_ns)
+
+
+def run(requests: np.ndarray, config: ServeConfig):
+    """Run the loop on the current device. ``requests`` is an array of
+    REQUEST_DTYPE (device pointers as integers). Returns (outcomes, stats)."""
+    requests = np.ascontiguousarray(requests, dtype=REQUEST_DTYPE)
+    outcomes = np.zeros(requests.size, dtype=OUTCOME_DTYPE)
+    st = ServeStats()
+    check(lib().utf16wf_serve_run(ctypes.addressof(config), requests.ctypes.data, requests.size,
+                                  outcomes.ctypes.data, ctypes.addressof(st)))
+    return outcomes, st.as_dict()
+
+
+def simulate(arrival_ns, lengths, config: ServeConfig, lat_base_ns=20_000, lat_ns_per_unit=0.001,
+             fail_every=0):
+    """The same scheduler on a simulated device with a virtual clock."""
+    arr = np.ascontiguousarray(arrival_ns, dtype=np.int64)
+    lens = np.ascontiguousarray(lengths, dtype=np.int64)
+    outcomes = np.zeros(arr.size, dtype=OUTCOME_DTYPE)
+    st = ServeStats()
+    check(lib().utf16wf_serve_simulate(ctypes.addressof(config), arr.ctypes.data, lens.ctypes.data, arr.size,
+                                       int(lat_base_ns), float(lat_ns_per_unit), int(fail_every),
+                                       outcomes.ctypes.data, ctypes.addressof(st)))
+    return outcomes, st.as_dict()
+
+
+def latency_summary(outcomes, arrival_ns, lengths):
+    """p50 / p99 / mean / max latency (ms) of completed requests, from their
+    scheduled arrival to the host seeing their batch complete; throughput in
+    GB/s of input over the run; GPU busy fraction (union of batch intervals)."""
+    ok = outcomes["status"] == 0
+    lat = (outcomes["done_ns"][ok] - np.asarray(arrival_ns)[ok]) / 1e6
+    res = {"completed": int(ok.sum())}
+    if lat.size:
+        res.update(p50_ms=round(float(np.percentile(lat, 50)), 4), p99_ms=round(float(np.percentile(lat, 99)), 4),
+                   mean_ms=round(float(lat.mean()), 4), max_ms=round(float(lat.max()), 4))
+        t_end = float(outcomes["done_ns"][ok].max())
+        t_start = float(np.asarray(arrival_ns)[ok].min())
+        res["input_GBps"] = round(2.0 * float(np.asarray(lengths)[ok].sum()) / max(t_end - t_start, 1.0), 3)
+        # union of [launch, done] over batches
+        b = outcomes[ok]
+        _, first = np.unique(b["batch"], return_index=True)
+        busy, cur_s, cur_e = 0, None, None
+        for s, e in sorted(map(tuple, np.stack([b["launch_ns"][first], b["done_ns"][first]], axis=1))):
+            if cur_e is None or s > cur_e:
+                if cur_e is not None:
+                    busy += cur_e - cur_s
+                cur_s, cur_e = s, e
+            else:
+                cur_e = max(cur_e, e)
+        if cur_e is not None:
+            busy += cur_e - cur_s
+        res["busy_frac"] = round(float(busy) / max(t_end - t_start, 1.0), 4)
+        res["batches"] = int(first.size)
+        res["mean_batch_requests"] = round(float(ok.sum()) / max(first.size, 1), 2)
+    return res
+
+
+def serve_workload(duration_s=5.0, rate_hz=50_000.0, num_streams=4, arena_bytes=64 << 30,
+                   max_batch_requests=4096, max_batch_units=1 << 26, op=OP_TO, seed=None,
+                   pool_len=1 << 24, n_pools=16, log=None):
+    """The serving workload: Poisson arrivals at ``rate_hz`` for
+    ``duration_s``, Zipf(1.1) lengths up to ``pool_len`` units, per-request
+    lone-surrogate rate 10^U(-6,-1), payloads sliced from device-resident
+    pools of mix(r_j) at log-spaced r_j. Returns a summary dict."""
+    import torch
+
+    from . import workloads as W
+    kw = {} if seed is None else {"seed": seed}
+    sch = W.serve_schedule(duration_s, rate_hz=rate_hz, n_pools=n_pools, pool_len=pool_len,
+                           max_len=pool_len, **kw)
+    if log:
+        log(f"serve: {sch['length'].size} requests, {int(sch['length'].sum())} units")
+    pools = W.serve_pools(sch["pool_rates"], pool_len=pool_len)
+    d_pools = [torch.from_numpy(p.view(np.int16)).cuda() for p in pools]
+    base = np.array([p.data_ptr() for p in d_pools], dtype=np.uint64)
+    reqs = np.zeros(sch["length"].size, dtype=REQUEST_DTYPE)
+    reqs["arrival_ns"] = sch["arrival_ns"]
+    reqs["src"] = base[sch["pool"]] + 2 * sch["pool_offset"].astype(np.uint64)
+    reqs["length"] = sch["length"]
+    torch.cuda.synchronize()
+    cfg = make_config(num_streams=num_streams, op=op, arena_bytes=arena_bytes,
+                      max_batch_requests=max_batch_requests, max_batch_units=max_batch_units)
+    out, st = run(reqs, cfg)
+    summ = latency_summary(out, sch["arrival_ns"], sch["length"])
+    summ.update({"requests": int(sch["length"].size), "duration_s": duration_s, "rate_hz": rate_hz,
+                 "num_streams": num_streams, "arena_bytes": arena_bytes, "stats": st})
+    del d_pools
+    return summ

@@ -1,0 +1,128 @@
+"""The serving loop on the GPU: every request's result in the mix equals its
+result alone (one flat launch on its own payload) and the oracle, exactly."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2601_06349_amd import workloads as W
+from tests.gpu_util import log, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = torch_mod()
+    import paper_2601_06349_amd as wf
+    from paper_2601_06349_amd import serve as S
+    rng = np.random.default_rng(2024)
+    pools = [W.mix(1 << 20, r, 300 + i) for i, r in enumerate((0.0, 1e-4, 1e-2, 0.2))]
+    pools.append(W.all_surrogates(1 << 20, 9))
+    d_pools = [torch.from_numpy(p.view(np.int16)).cuda() for p in pools]
+    n = 3000
+    lens = np.minimum(W.zipf_lengths(n, rng, max_len=1 << 18), 1 << 18)
+    lens[::97] = 0
+    lens[[10, 500, 2000]] = [1 << 18, 200_001, 150_000]
+    pool = rng.integers(0, len(pools), size=n)
+    offs = np.array([rng.integers(0, (1 << 20) - L + 1) for L in lens])
+    arrival = np.cumsum(rng.exponential(1e9 / 200_000, size=n)).astype(np.int64)  # 200k req/s
+    # destinations: one buffer, requests at varied alignments
+    dst_off = np.zeros(n, dtype=np.int64)
+    pos = 3
+    for i in range(n):
+        dst_off[i] = pos
+        pos += int(lens[i]) + int(rng.integers(0, 9))
+    d_dst = torch.full((pos + 8,), 0x1234, dtype=torch.int16, device="cuda")
+    want = [oracle.to_well_formed(pools[pool[i]][offs[i]:offs[i] + lens[i]]) for i in range(n)]
+    torch.cuda.synchronize()
+    return dict(torch=torch, wf=wf, S=S, pools=pools, d_pools=d_pools, lens=lens, pool=pool, offs=offs,
+                arrival=arrival, dst_off=dst_off, d_dst=d_dst, want=want, n=n)
+
+
+def _requests(e, with_dst=True):
+    S = e["S"]
+    reqs = np.zeros(e["n"], dtype=S.REQUEST_DTYPE)
+    base = np.array([p.data_ptr() for p in e["d_pools"]], dtype=np.uint64)
+    reqs["arrival_ns"] = e["arrival"]
+    reqs["src"] = base[e["pool"]] + 2 * e["offs"].astype(np.uint64)
+    reqs["length"] = e["lens"]
+    if with_dst:
+        reqs["dst"] = np.uint64(e["d_dst"].data_ptr()) + 2 * e["dst_off"].astype(np.uint64)
+    return reqs
+
+
+def _check_outputs(e, what):
+    host = e["d_dst"].cpu().numpy().view(np.uint16)
+    bad = []
+    for i in range(e["n"]):
+        got = host[e["dst_off"][i]:e["dst_off"][i] + e["lens"][i]]
+        if not np.array_equal(got, e["want"][i]):
+            bad.append(i)
+    assert not bad, f"{what}: {len(bad)} requests differ, first {bad[:5]}"
+
+
+@pytest.mark.parametrize("streams,arena,max_req", [(4, 1 << 30, 256), (1, 8 << 20, 16), (8, 64 << 20, 4096)])
+def test_mix_equals_alone_and_oracle(env, streams, arena, max_req):
+    torch, S = env["torch"], env["S"]
+    env["d_dst"].fill_(0x1234)
+    cfg = S.make_config(num_streams=streams, arena_bytes=arena, max_batch_requests=max_req,
+                        max_batch_units=1 << 22)
+    out, st = S.run(_requests(env), cfg)
+    log(f"serve streams={streams} arena={arena}: {st}")
+    assert np.all(out["status"] == 0), np.unique(out["status"])
+    assert st["completed"] == env["n"] and st["arena_peak_bytes"] <= arena
+    _check_outputs(env, f"served streams={streams}")
+    if streams > 1:
+        # the mix really happened: batches of several requests, overlapping on the GPU
+        assert st["max_inflight"] > 1
+        assert st["batches"] < env["n"]
+
+
+def test_alone_launches_equal_oracle(env):
+    """The same requests, one flat launch each (alone), equal the oracle."""
+    torch, wf = env["torch"], env["wf"]
+    env["d_dst"].fill_(0x1234)
+    L = wf.lib()
+    stream = torch.cuda.current_stream().cuda_stream
+    dst = env["d_dst"].data_ptr()
+    for i in range(env["n"]):
+        if env["lens"][i] == 0:
+            continue
+        src = env["d_pools"][env["pool"][i]].data_ptr() + 2 * int(env["offs"][i])
+        assert L.utf16_to_well_formed(src, dst + 2 * int(env["dst_off"][i]), int(env["lens"][i]), stream) == 0
+    torch.cuda.synchronize()
+    _check_outputs(env, "alone")
+
+
+def test_serve_is_well_formed(env):
+    S = env["S"]
+    cfg = S.make_config(num_streams=4, op=env["wf"].OP_IS, arena_bytes=1 << 30, max_batch_requests=512)
+    out, st = S.run(_requests(env, with_dst=False), cfg)
+    assert np.all(out["status"] == 0)
+    want = np.array([int(np.array_equal(w, env["pools"][env["pool"][i]][env["offs"][i]:env["offs"][i] +
+                                                                          env["lens"][i]]))
+                     for i, w in enumerate(env["want"])])
+    assert np.array_equal(out["well_formed"], want)
+
+
+def test_oversize_rejected(env):
+    S, wf = env["S"], env["wf"]
+    cfg = S.make_config(num_streams=2, arena_bytes=1 << 20, max_batch_requests=64)
+    out, st = S.run(_requests(env, with_dst=False), cfg)
+    r = lambda b: (b + 255) // 256 * 256
+    big = np.array([2 * r(2 * int(L)) + r(16) + r(1) > (1 << 20) for L in env["lens"]])
+    assert np.all(out["status"][big] == wf.ERANGE)
+    assert np.all(out["status"][~big] == 0)
+    assert st["rejected"] == int(big.sum())
+
+
+def test_serve_workload_short(env):
+    """A short run of the serving workload (Poisson 50k req/s, Zipf lengths)."""
+    S = env["S"]
+    summ = S.serve_workload(duration_s=0.5, rate_hz=50_000, num_streams=4, arena_bytes=8 << 30,
+                            pool_len=1 << 22, n_pools=4, log=log)
+    log(f"serve workload: {summ}")
+    assert summ["completed"] == summ["requests"]
+    assert summ["p99_ms"] >= summ["p50_ms"] > 0

@@ -1,0 +1,154 @@
+"""The serving loop's scheduler on a simulated device (virtual clock, no
+GPU): admission under the HBM budget, arrival order, continuous batching,
+concurrency limit, time-outs, launch-failure handling."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import paper_2601_06349_amd as wf
+from paper_2601_06349_amd import serve as S
+
+
+def _layout_bytes(nreq, units):
+    r = lambda b: (b + 255) // 256 * 256
+    return 2 * r(2 * units) + r(8 * (nreq + 1)) + r(max(nreq, 1))
+
+
+def test_budget_and_rejection():
+    rng = np.random.default_rng(0)
+    n = 400
+    arr = np.sort(rng.integers(0, 2_000_000, size=n))
+    lens = rng.integers(0, 20_000, size=n)
+    lens[[5, 77]] = 1_000_000  # larger than the whole arena
+    arena = 200_000
+    cfg = S.make_config(num_streams=3, arena_bytes=arena, max_batch_requests=16, max_batch_units=50_000)
+    out, st = S.simulate(arr, lens, cfg, lat_base_ns=5_000, lat_ns_per_unit=2.0)
+    assert st["arena_peak_bytes"] <= arena
+    assert list(np.nonzero(out["status"] == wf.ERANGE)[0]) == [5, 77]
+    assert st["rejected"] == 2 and st["completed"] == n - 2
+    assert np.all(out["status"][out["status"] != wf.ERANGE] == 0)
+    # every batch fits the arena and respects the limits
+    for b in np.unique(out["batch"][out["batch"] >= 0]):
+        m = out["batch"] == b
+        assert m.sum() <= 16
+        assert lens[m].sum() <= 50_000 or m.sum() == 1
+        assert _layout_bytes(int(m.sum()), int(lens[m].sum())) <= arena
+    assert st["max_inflight"] <= 3
+
+
+def test_arrival_order_and_no_early_launch():
+    rng = np.random.default_rng(1)
+    n = 1000
+    arr = np.cumsum(rng.exponential(2_000, size=n)).astype(np.int64)
+    lens = rng.integers(1, 5_000, size=n)
+    cfg = S.make_config(num_streams=4, arena_bytes=1 << 30, max_batch_requests=64, max_batch_units=100_000)
+    out, st = S.simulate(arr, lens, cfg, lat_base_ns=30_000, lat_ns_per_unit=1.0)
+    assert np.all(out["status"] == 0)
+    assert np.all(out["launch_ns"] >= arr)
+    assert np.all(out["done_ns"] > out["launch_ns"])
+    # admitted in arrival order: batch ids never decrease along the arrivals
+    assert np.all(np.diff(out["batch"]) >= 0)
+
+
+def test_continuous_batching_fills_next_batch():
+    """One slot, 100 us per batch, a request every 10 us: the first batch holds
+    one request and each later batch holds every request that arrived while
+    the previous one was on the device."""
+    n = 50
+    arr = np.arange(n, dtype=np.int64) * 10_000
+    lens = np.full(n, 100)
+    cfg = S.make_config(num_streams=1, arena_bytes=1 << 30, max_batch_requests=1000, max_batch_units=1 << 30)
+    out, st = S.simulate(arr, lens, cfg, lat_base_ns=100_000, lat_ns_per_unit=0.0)
+    assert out["batch"][0] == 0 and np.sum(out["batch"] == 0) == 1
+    sizes = np.bincount(out["batch"])
+    assert np.all(sizes[1:-1] == 10), sizes
+    for b in range(1, sizes.size):
+        m = out["batch"] == b
+        t = out["launch_ns"][m][0]
+        waiting = (arr <= t) & (out["batch"] >= b)
+        assert np.array_equal(np.nonzero(waiting)[0], np.nonzero(m)[0])
+
+
+def test_overlap_uses_all_slots():
+    n = 200
+    arr = np.zeros(n, dtype=np.int64)
+    lens = np.full(n, 1000)
+    cfg = S.make_config(num_streams=4, arena_bytes=1 << 30, max_batch_requests=5, max_batch_units=1 << 30)
+    out, st = S.simulate(arr, lens, cfg, lat_base_ns=50_000)
+    assert st["max_inflight"] == 4
+    assert st["batches"] == 40
+    assert len(np.unique(out["slot"])) == 4
+
+
+def test_memory_blocks_admission_until_free():
+    """Two requests that each need most of the arena run one after the other
+    even with free slots."""
+    arena = _layout_bytes(1, 30_000) + 1000
+    arr = np.zeros(3, dtype=np.int64)
+    lens = np.array([30_000, 30_000, 10])
+    cfg = S.make_config(num_streams=4, arena_bytes=arena, max_batch_requests=1, max_batch_units=1 << 30)
+    out, st = S.simulate(arr, lens, cfg, lat_base_ns=10_000)
+    assert out["launch_ns"][1] >= out["done_ns"][0]
+    assert out["launch_ns"][2] >= out["launch_ns"][1]  # arrival order is kept
+    assert st["max_inflight"] == 1
+
+
+def test_timeouts():
+    n = 100
+    arr = np.zeros(n, dtype=np.int64)
+    lens = np.full(n, 10)
+    cfg = S.make_config(num_streams=1, arena_bytes=1 << 30, max_batch_requests=1, max_batch_units=1 << 30,
+                        timeout_ns=250_000)
+    out, st = S.simulate(arr, lens, cfg, lat_base_ns=100_000)
+    assert st["timed_out"] > 0 and st["completed"] + st["timed_out"] == n
+    assert np.all(out["status"][:3] == 0)
+    assert np.all((out["status"] == 0) | (out["status"] == 1))
+
+
+def test_launch_failures_are_reported_and_loop_continues():
+    n = 60
+    arr = np.arange(n, dtype=np.int64) * 1000
+    lens = np.full(n, 10)
+    cfg = S.make_config(num_streams=2, arena_bytes=1 << 30, max_batch_requests=1, max_batch_units=1 << 30)
+    out, st = S.simulate(arr, lens, cfg, lat_base_ns=5_000, fail_every=3)
+    assert st["failed"] == 20 and st["completed"] == 40
+    assert np.all(out["status"][2::3] == wf.EHIP)
+    assert st["arena_peak_bytes"] > 0
+
+
+def test_deterministic_and_edge_cases():
+    rng = np.random.default_rng(5)
+    arr = np.sort(rng.integers(0, 10_000_000, size=300))
+    lens = rng.integers(0, 3, size=300)  # many empty requests
+    cfg = S.make_config(num_streams=2, arena_bytes=1 << 20, max_batch_requests=7, max_batch_units=1000)
+    a, sa = S.simulate(arr, lens, cfg)
+    b, sb = S.simulate(arr, lens, cfg)
+    assert np.array_equal(a, b) and sa == sb
+    assert np.all(a["status"] == 0)
+    out, st = S.simulate(np.zeros(0, np.int64), np.zeros(0, np.int64), cfg)
+    assert st["batches"] == 0
+
+
+def test_argument_errors():
+    cfg = S.make_config(num_streams=0)
+    with pytest.raises(wf.Utf16wfError):
+        S.simulate([0], [1], cfg)
+    cfg = S.make_config(num_streams=2)
+    with pytest.raises(wf.Utf16wfError):
+        S.simulate([5, 3], [1, 1], cfg)
+    with pytest.raises(wf.Utf16wfError):
+        S.simulate([0], [-1], cfg)
+    cfg = S.make_config(num_streams=2, op=wf.OP_LOCATE)
+    with pytest.raises(wf.Utf16wfError):
+        S.simulate([0], [1], cfg)
+
+
+def test_latency_summary():
+    arr = np.arange(10, dtype=np.int64) * 1_000_000
+    lens = np.full(10, 1000)
+    cfg = S.make_config(num_streams=1)
+    out, st = S.simulate(arr, lens, cfg, lat_base_ns=500_000)
+    s = S.latency_summary(out, arr, lens)
+    assert s["completed"] == 10 and abs(s["p50_ms"] - 0.5) < 1e-6 and abs(s["p99_ms"] - 0.5) < 1e-6
+    assert 0.0 < s["busy_frac"] <= 1.0
