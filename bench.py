@@ -173,6 +173,95 @@ def per_string_vs_batched(torch, wf, stream, sample=20000):
     }
 
 
+def zipf_tuned_vs_default(torch, wf, tune, stream):
+    """The 4096-string Zipf(1.1) batch (up to 2^24 units per string): copy
+    repair, in-place repair and isWellFormed with early exit, each with the
+    autotuned launch shape and with the built-in default."""
+    from paper_2601_06349_amd import workloads as W
+    buf, off, kind = W.zipf_batch()
+    n = int(off[-1])
+    t_in = torch.from_numpy(buf.view(np.int16)).cuda()
+    t_off = torch.from_numpy(off).cuda()
+    t_out = torch.empty_like(t_in)
+    t_ip = torch.empty_like(t_in)
+    res = torch.empty(off.size - 1, dtype=torch.uint8, device="cuda")
+    calls = {
+        "to": (lambda: wf.utf16_to_well_formed_batch(t_in, t_off, out=t_out), None, 4 * n),
+        "to_inplace": (lambda: wf.utf16_to_well_formed_batch_inplace(t_ip, t_off), lambda: t_ip.copy_(t_in),
+                       2 * n),
+        "is": (lambda: wf.utf16_is_well_formed_batch(t_in, t_off, results=res), None, 2 * n),
+    }
+    out = {"workload": f"4096 strings, Zipf(1.1) lengths over 1..2^24, {n} units, "
+                       f"{int(kind.sum())} strings mix(1e-2), the rest ASCII"}
+    for name, (fn, setup, algo_bytes) in calls.items():
+        wf.reset_params()
+        d_ms, _ = time_fn(torch, stream, fn, reps=5, setup=setup)
+        tune.apply_cache()
+        t_ms, _ = time_fn(torch, stream, fn, reps=5, setup=setup)
+        out[name] = {"default_ms": round(d_ms, 4), "tuned_ms": round(t_ms, 4),
+                     "tuned_input_GBps": round(2 * n / (t_ms * 1e-3) / 1e9, 1),
+                     "tuned_pct_hbm_full_pass": round(100 * algo_bytes / (t_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 1)}
+    del t_in, t_out, t_ip
+    torch.cuda.empty_cache()
+    return out
+
+
+def paper_workloads(torch, wf, stream):
+    """The paper's own shapes (Sec. 4, Sec. 4.1): 1,000,000 units at 0.1 %
+    pairs with 0 % and 0.1 % mismatched; 128 sizes up to 1,000,000 units; the
+    1024-unit JavaScript string with 5 % lows and 5 % highs. Each as one flat
+    launch and as a batch of many such strings in one launch."""
+    from paper_2601_06349_amd import workloads as W
+    res = {}
+    for label, mis in (("1M_pairs0.1_mis0", 0.0), ("1M_pairs0.1_mis0.1", 0.1)):
+        s = W.paper_mix(1_000_000, 0.1, mis, W.SEEDS["paper_1m"])
+        d = torch.from_numpy(s.view(np.int16)).cuda()
+        o = torch.empty_like(d)
+        med, best = time_fn(torch, stream, lambda: wf.utf16_to_well_formed(d, o), reps=50)
+        k = 64
+        big = W.paper_mix(1_000_000 * k, 0.1, mis, W.SEEDS["paper_1m"] + 1)
+        offs = torch.arange(0, 1_000_000 * (k + 1), 1_000_000, dtype=torch.int64, device="cuda")
+        db = torch.from_numpy(big.view(np.int16)).cuda()
+        ob = torch.empty_like(db)
+        bmed, _ = time_fn(torch, stream, lambda: wf.utf16wf_batch(wf.OP_TO, db, offs, out=ob,
+                                                                  units_hint=big.size), reps=20)
+        res[label] = {"flat_us": round(med * 1e3, 2), "flat_best_us": round(best * 1e3, 2),
+                      "flat_input_GBps": round(2e6 / (med * 1e-3) / 1e9, 1),
+                      "batch_of_64_input_GBps": round(2 * big.size / (bmed * 1e-3) / 1e9, 1)}
+    sizes = np.linspace(1_000_000 / 128, 1_000_000, 128).astype(np.int64)
+    s = W.paper_mix(1_000_000, 0.1, 0.1, W.SEEDS["paper_sweep"])
+    d = torch.from_numpy(s.view(np.int16)).cuda()
+    o = torch.empty_like(d)
+    rates = []
+    for n in sizes:
+        x, y = d[:n], o[:n]
+        med, _ = time_fn(torch, stream, lambda: wf.utf16_to_well_formed(x, y), reps=10)
+        rates.append(2 * int(n) / (med * 1e-3) / 1e9)
+    res["size_sweep_128"] = {"sizes": f"{sizes[0]}..{sizes[-1]} units", "input_GBps_min": round(min(rates), 1),
+                             "input_GBps_max": round(max(rates), 1),
+                             "input_GBps_at_1M": round(rates[-1], 1)}
+    js = W.js_string()
+    d = torch.from_numpy(js.view(np.int16)).cuda()
+    o = torch.empty_like(d)
+    med, _ = time_fn(torch, stream, lambda: wf.utf16_to_well_formed(d, o), reps=100)
+    k = 1 << 18
+    rng = np.random.default_rng(W.SEEDS["js_1024"] + 1)
+    many = np.concatenate([W.js_string(seed=rng) for _ in range(64)])
+    many = np.tile(many, k // 64)
+    offs = torch.arange(0, 1024 * (k + 1), 1024, dtype=torch.int64, device="cuda")
+    db = torch.from_numpy(many.view(np.int16)).cuda()
+    ob = torch.empty_like(db)
+    bmed, _ = time_fn(torch, stream, lambda: wf.utf16wf_batch(wf.OP_TO, db, offs, out=ob, units_hint=many.size),
+                      reps=20)
+    res["js_1024_5pct_low_5pct_high"] = {
+        "flat_us": round(med * 1e3, 2), "flat_input_GiBps": round(2048 / (med * 1e-3) / 2**30, 2),
+        "batch_of_262144_input_GiBps": round(2 * many.size / (bmed * 1e-3) / 2**30, 1),
+        "batch_us_per_string": round(bmed * 1e3 / k, 5)}
+    del db, ob
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -180,6 +269,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true", help="only the timed steps, roofline and CPU baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--serve-seconds", type=float, default=5.0, help="length of the serving run")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: the steps plus one copy-kernel launch, no extras")
     args = ap.parse_args()
@@ -300,6 +390,18 @@ def main():
         del scratch
         log("extras: batched vs per-string")
         ex["ragged_batch"] = per_string_vs_batched(torch, wf, stream)
+        del d_out
+        torch.cuda.empty_cache()
+        log("extras: Zipf batch, tuned vs default")
+        ex["zipf_batch"] = zipf_tuned_vs_default(torch, wf, tune, stream)
+        log("extras: the paper's workloads")
+        ex["paper_workloads"] = paper_workloads(torch, wf, stream)
+        log("extras: serving loop")
+        from paper_2601_06349_amd import serve as S
+        sv = S.serve_workload(duration_s=args.serve_seconds, rate_hz=50_000, num_streams=4,
+                              arena_bytes=64 << 30, log=log)
+        ex["serve"] = sv
+        result["serve_p99_ms"] = sv.get("p99_ms")
         result["extras"] = ex
 
     print(json.dumps(result), flush=True)
