@@ -262,6 +262,26 @@ def paper_workloads(torch, wf, stream):
     return res
 
 
+def host_resident(torch, wf, host_input):
+    """The same 512 MiB repair when the string lives in pinned host memory:
+    chunked copy in, repair and copy out on overlapping streams (PCIe-bound;
+    never the headline value)."""
+    n = host_input.size
+    pin_in = torch.empty(n, dtype=torch.int16, pin_memory=True)
+    pin_out = torch.empty(n, dtype=torch.int16, pin_memory=True)
+    a = pin_in.numpy().view(np.uint16)
+    b = pin_out.numpy().view(np.uint16)
+    a[:] = host_input
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        wf.utf16_to_well_formed_host(a, out=b)
+        times.append(time.perf_counter() - t0)
+    best = min(times)
+    return {"units": n, "best_s": round(best, 4), "input_GBps": round(2 * n / best / 1e9, 2),
+            "note": "pinned host in and out, 16 Mi-unit chunks on 3 streams; includes both PCIe transfers"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -396,6 +416,8 @@ def main():
         ex["zipf_batch"] = zipf_tuned_vs_default(torch, wf, tune, stream)
         log("extras: the paper's workloads")
         ex["paper_workloads"] = paper_workloads(torch, wf, stream)
+        log("extras: host-resident input")
+        ex["host_resident"] = host_resident(torch, wf, host_inputs[2])
         log("extras: serving loop")
         from paper_2601_06349_amd import serve as S
         sv = S.serve_workload(duration_s=args.serve_seconds, rate_hz=50_000, num_streams=4,

@@ -85,6 +85,19 @@ int utf16_to_well_formed_inplace(uint16_t *buf, int64_t n, void *stream);
 int utf16_locate_ill_formed(const uint16_t *in, int64_t n, int64_t *first_bad, int64_t *count,
                             void *stream);
 
+/* Host-resident input (not in the paper's interface; the paper's routine
+ * repairs strings in the CPU's memory, Sec. 4): toWellFormed of h_in[0, n)
+ * into h_out[0, n), both HOST memory (h_out == h_in repairs in place; any
+ * other overlap is UTF16WF_EOVERLAP). The string moves through device
+ * staging buffers in chunks of chunk_units (0 = 16 Mi units); each chunk is
+ * copied in with one unit of context on each side, repaired, and its own
+ * units copied back. Copies in, repairs and copies out of successive chunks
+ * run on separate streams and overlap when the host buffers are pinned
+ * (hipHostMalloc); pageable buffers work but are staged by the runtime.
+ * Synchronous: returns when h_out is complete. Staging memory is allocated
+ * per call and freed before returning. */
+int utf16_to_well_formed_host(const uint16_t *h_in, uint16_t *h_out, int64_t n, int64_t chunk_units);
+
 /* -------------------------------------------------------- ragged batch --- */
 /* offsets: device int64[num_strings + 1], non-decreasing, offsets[0] >= 0;
  * string k is units [offsets[k], offsets[k+1]) of the packed buffer. The

@@ -24,7 +24,7 @@ from ._lib import (EALIGN, EHIP, EINVAL, ENOMEM, EOFFSETS, EOVERLAP, ERANGE, OK,
 
 __all__ = [
     "utf16_is_well_formed", "utf16_to_well_formed", "utf16_to_well_formed_inplace",
-    "utf16_locate_ill_formed", "utf16_is_well_formed_batch", "utf16_to_well_formed_batch",
+    "utf16_locate_ill_formed", "utf16_to_well_formed_host", "utf16_is_well_formed_batch", "utf16_to_well_formed_batch",
     "utf16_to_well_formed_batch_inplace", "utf16_locate_ill_formed_batch", "utf16wf_batch",
     "utf16wf_validate_offsets", "BatchPlan", "is_well_formed", "set_params", "get_params",
     "reset_params", "utf16wf_copy_units", "device_cus", "Utf16wfError", "lib", "last_error",
@@ -98,6 +98,23 @@ def utf16_to_well_formed_inplace(t, stream=None):
     _units(t)
     check(lib().utf16_to_well_formed_inplace(t.data_ptr(), t.numel(), _stream(stream)))
     return t
+
+
+def utf16_to_well_formed_host(arr, out=None, chunk_units=0):
+    """Repair a host-resident numpy uint16 array (``out`` may be ``arr`` for
+    in place) through device staging in overlapped chunks; returns ``out``.
+    Pinned host memory (e.g. the numpy view of a torch ``pin_memory``
+    tensor) lets copies and repairs overlap."""
+    import numpy as np
+    if not isinstance(arr, np.ndarray) or arr.dtype not in (np.uint16, np.int16) or arr.ndim != 1 \
+            or not arr.flags.c_contiguous:
+        raise TypeError("arr must be a contiguous 1-D numpy uint16 array")
+    if out is None:
+        out = np.empty_like(arr)
+    if out.shape != arr.shape or out.dtype != arr.dtype or not out.flags.c_contiguous:
+        raise ValueError("out must match arr")
+    check(lib().utf16_to_well_formed_host(arr.ctypes.data, out.ctypes.data, arr.size, int(chunk_units)))
+    return out
 
 
 def utf16_locate_ill_formed(t, stream=None):

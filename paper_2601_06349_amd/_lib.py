@@ -59,6 +59,7 @@ SIGNATURES = {
     "utf16_to_well_formed": (_INT, [_P, _P, _I64, _P]),
     "utf16_to_well_formed_inplace": (_INT, [_P, _I64, _P]),
     "utf16_locate_ill_formed": (_INT, [_P, _I64, _P, _P, _P]),
+    "utf16_to_well_formed_host": (_INT, [_P, _P, _I64, _I64]),
     "utf16_is_well_formed_batch": (_INT, [_P, _P, _I64, _P, _P]),
     "utf16_to_well_formed_batch": (_INT, [_P, _P, _P, _I64, _P]),
     "utf16_to_well_formed_batch_inplace": (_INT, [_P, _P, _I64, _P]),

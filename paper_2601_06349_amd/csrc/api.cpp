@@ -541,6 +541,63 @@ int utf16wf_reset_params(void) {
     return UTF16WF_OK;
 }
 
+int utf16_to_well_formed_host(const uint16_t *h_in, uint16_t *h_out, int64_t n, int64_t chunk_units) {
+    if (n < 0 || chunk_units < 0)
+        return fail(UTF16WF_EINVAL, "negative size");
+    if (n == 0)
+        return UTF16WF_OK;
+    if (!h_in || !h_out)
+        return fail(UTF16WF_EINVAL, "null pointer");
+    int rc;
+    if ((rc = check_u16(h_in, "h_in")) != UTF16WF_OK || (rc = check_u16(h_out, "h_out")) != UTF16WF_OK)
+        return rc;
+    if (overlap_not_equal(h_in, h_out, n))
+        return fail(UTF16WF_EOVERLAP, "host input and output overlap without being equal");
+    const int64_t chunk = std::min<int64_t>(n, chunk_units > 0 ? chunk_units : (int64_t)1 << 24);
+    constexpr int kStages = 3;
+    const int64_t nchunks = (n + chunk - 1) / chunk;
+    const int stages = (int)std::min<int64_t>(kStages, nchunks);
+    uint16_t *d_buf = nullptr;
+    hipStream_t st[kStages] = {nullptr, nullptr, nullptr};
+    // input and output staging of every stage start 128-byte aligned
+    const int64_t stride = (chunk + 2 + 63) / 64 * 64;
+    hipError_t e = hipMalloc((void **)&d_buf, (size_t)stages * 2 * (size_t)stride * sizeof(uint16_t));
+    if (e != hipSuccess)
+        return hip_fail(e, "hipMalloc(staging)");
+    rc = UTF16WF_OK;
+    for (int i = 0; i < stages && rc == UTF16WF_OK; ++i)
+        if ((e = hipStreamCreateWithFlags(&st[i], hipStreamNonBlocking)) != hipSuccess)
+            rc = hip_fail(e, "hipStreamCreateWithFlags");
+    for (int64_t c = 0; c < nchunks && rc == UTF16WF_OK; ++c) {
+        const int s = (int)(c % stages);
+        uint16_t *d_in = d_buf + (size_t)s * 2 * stride;
+        uint16_t *d_out = d_in + stride;
+        const int64_t a = c * chunk, b = std::min(n, a + chunk);
+        const int64_t ca = a > 0 ? a - 1 : a, cb = b < n ? b + 1 : b;  // one unit of context each side
+        if ((e = hipMemcpyAsync(d_in, h_in + ca, (size_t)(cb - ca) * 2, hipMemcpyHostToDevice, st[s])) !=
+            hipSuccess) {
+            rc = hip_fail(e, "copy in");
+            break;
+        }
+        if ((rc = utf16_to_well_formed(d_in, d_out, cb - ca, st[s])) != UTF16WF_OK)
+            break;
+        if ((e = hipMemcpyAsync(h_out + a, d_out + (a - ca), (size_t)(b - a) * 2, hipMemcpyDeviceToHost, st[s])) !=
+            hipSuccess) {
+            rc = hip_fail(e, "copy out");
+            break;
+        }
+    }
+    for (int i = 0; i < stages; ++i) {
+        if (st[i]) {
+            if ((e = hipStreamSynchronize(st[i])) != hipSuccess && rc == UTF16WF_OK)
+                rc = hip_fail(e, "synchronize");
+            (void)hipStreamDestroy(st[i]);
+        }
+    }
+    (void)hipFree(d_buf);
+    return rc;
+}
+
 int utf16wf_copy_units(const uint16_t *in, uint16_t *out, int64_t n, void *stream) {
     if (n < 0)
         return fail(UTF16WF_EINVAL, "n < 0");

@@ -235,7 +235,19 @@ template <int OP, bool BATCH, int R, bool NT, bool SS>
 __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
     constexpr int64_t T = kRowUnits * R;
     constexpr int kWords = 16 * R;
+    constexpr bool kFlatLocate = (OP == kOpLocate && !BATCH);
     __shared__ uint32_t s_bm[BATCH ? kMaxWgWaves * kWords : 1];
+    // flat OP_LOCATE: per-workgroup totals, published by the last wave
+    __shared__ unsigned long long s_loc_first;
+    __shared__ uint32_t s_loc_count, s_loc_done;
+    if constexpr (kFlatLocate) {
+        if (threadIdx.x == 0) {
+            s_loc_first = ~0ull;
+            s_loc_count = 0u;
+            s_loc_done = 0u;
+        }
+        __syncthreads();
+    }
 
     const int lane = __lane_id();
     const int wslot = threadIdx.x >> 6;
@@ -258,17 +270,32 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
     const int64_t per = (t1 - t0 + nwaves - 1) / nwaves;
     const int64_t tb = t0 + wave * per;
     const int64_t te = min(tb + per, t1);
-    if (tb >= te)
-        return;
+    if (tb >= te && !kFlatLocate)
+        return;  // (flat locate waves without tiles still report to their workgroup)
 
     uint32_t *bm = BATCH ? s_bm + wslot * kWords : nullptr;
     int64_t cursor = 0;
     if constexpr (BATCH)
         cursor = lower_bound_wave(off, a.nstr + 1, tb * T - shift, lane);
 
-    // flat OP_LOCATE accumulators
+    // OP_LOCATE accumulators: count per lane, first index per wave. Flat:
+    // the whole run; batch: consecutive tiles that lie inside one string
+    // (loc_k), flushed with one pair of atomics when the string changes.
     uint64_t loc_first = ~0ull;
     uint32_t loc_count = 0;
+    int64_t loc_k = -1;
+    auto loc_flush = [&]() {
+        uint32_t c = loc_count;
+#pragma unroll
+        for (int sh = 32; sh >= 1; sh >>= 1)
+            c += __shfl_xor(c, sh);
+        if (lane == 0 && c != 0) {
+            atomicAdd(reinterpret_cast<unsigned long long *>(a.count + loc_k), (unsigned long long)c);
+            atomicMin(reinterpret_cast<unsigned long long *>(a.first + loc_k), (unsigned long long)loc_first);
+        }
+        loc_count = 0;
+        loc_first = ~0ull;
+    };
 
     // flat OP_IS early exit: the result word drops to 0 once any wave has
     // seen a mismatch. The first poll waits (a wave that starts late skips
@@ -312,6 +339,15 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
         if constexpr (BATCH && OP != kOpIs) {
             ts = scan_starts<R>(off, a.nstr, shift, cursor, tl, th, bm, lane);
             cursor = ts.knext;
+        }
+        // batch locate: does the whole tile lie inside one string?
+        const bool single = BATCH && !ts.inner && ts.kc >= 0 && ts.kc < a.nstr;
+        if constexpr (OP == kOpLocate && BATCH) {
+            if (single && ts.kc != loc_k) {
+                if (loc_k >= 0)
+                    loc_flush();
+                loc_k = ts.kc;
+            }
         }
 
         // classify every row; ballot the two flags neighbours need
@@ -409,14 +445,15 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
                     }
                 }
             } else {  // kOpLocate
-                if constexpr (!BATCH) {
+                if (!BATCH || single) {
                     if (wave_bad) {
                         loc_count += (uint32_t)__popcll(bad64);
                         if (loc_first == ~0ull) {
                             const int fl = __builtin_ctzll(wave_bad);
                             const int j = lane_bad ? (__builtin_ctzll(bad64) >> 3) : 0;
                             const int jf = __shfl(j, fl);
-                            loc_first = (uint64_t)(tl + ((int64_t)r * 64 + fl) * 8 + jf - lo);
+                            const int64_t base = BATCH ? off[loc_k] + shift : lo;
+                            loc_first = (uint64_t)(tl + ((int64_t)r * 64 + fl) * 8 + jf - base);
                         }
                     }
                 } else {
@@ -437,14 +474,32 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
         }
     }
 
-    if constexpr (OP == kOpLocate && !BATCH) {
+    if constexpr (OP == kOpLocate && BATCH) {
+        if (loc_k >= 0)
+            loc_flush();
+    }
+    if constexpr (kFlatLocate) {
+        // wave totals -> workgroup totals in LDS -> one pair of global
+        // atomics by the last wave of the workgroup to finish
         uint32_t c = loc_count;
 #pragma unroll
-        for (int s = 32; s >= 1; s >>= 1)
-            c += __shfl_xor(c, s);
-        if (lane == 0 && c != 0) {
-            atomicAdd(reinterpret_cast<unsigned long long *>(a.count), (unsigned long long)c);
-            atomicMin(reinterpret_cast<unsigned long long *>(a.first), (unsigned long long)loc_first);
+        for (int sh = 32; sh >= 1; sh >>= 1)
+            c += __shfl_xor(c, sh);
+        if (lane == 0) {
+            if (c != 0) {
+                atomicAdd(&s_loc_count, c);
+                atomicMin(&s_loc_first, (unsigned long long)loc_first);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (atomicAdd(&s_loc_done, 1u) == (uint32_t)wg_waves - 1u) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                const uint32_t tc = atomicAdd(&s_loc_count, 0u);
+                const unsigned long long tf = atomicMin(&s_loc_first, ~0ull);
+                if (tc != 0) {
+                    atomicAdd(reinterpret_cast<unsigned long long *>(a.count), (unsigned long long)tc);
+                    atomicMin(reinterpret_cast<unsigned long long *>(a.first), tf);
+                }
+            }
         }
     }
 }

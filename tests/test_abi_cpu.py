@@ -73,6 +73,19 @@ def test_flat_argument_errors(L):
     assert "alignment" in msg or "aligned" in msg
 
 
+def test_host_path_argument_errors(L):
+    import numpy as np
+    from paper_2601_06349_amd import EALIGN, EINVAL, EOVERLAP
+    s = np.zeros(10, np.uint16)
+    p = s.ctypes.data
+    assert _rc(L, "utf16_to_well_formed_host", p, p + 2, 10, 0) == EOVERLAP
+    assert _rc(L, "utf16_to_well_formed_host", p, p + 1, 10, 0) == EALIGN
+    assert _rc(L, "utf16_to_well_formed_host", None, p, 10, 0) == EINVAL
+    assert _rc(L, "utf16_to_well_formed_host", p, p, -1, 0) == EINVAL
+    assert _rc(L, "utf16_to_well_formed_host", p, p, 10, -5) == EINVAL
+    assert _rc(L, "utf16_to_well_formed_host", p, p, 0, 0) == 0
+
+
 def test_batch_argument_errors(L):
     from paper_2601_06349_amd import EALIGN, EINVAL
     assert _rc(L, "utf16_to_well_formed_batch", A, A + 4096, A + 8192, -1, None) == EINVAL

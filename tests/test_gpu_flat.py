@@ -191,3 +191,51 @@ def test_single_buffer_full_size(wf, variant):
         assert abs(cnt / s.size - 0.5) < 0.01  # about half of the units pair up
     del t_in, t_out
     torch.cuda.empty_cache()
+
+
+def test_beyond_32bit_indices(wf):
+    """A buffer of 2^31 + 2^20 + 3 units (4.3 GB): mismatches planted around
+    unit 2^31 and near the end; outputs checked on windows against the oracle
+    (a unit's result depends only on its two neighbours, so a window with one
+    unit of margin on each side is exact)."""
+    torch = torch_mod()
+    n = (1 << 31) + (1 << 20) + 3
+    t = torch.full((n,), A, dtype=torch.int16, device="cuda")
+    plants = {(1 << 31) - 2: [H, H, L], (1 << 31) + 7: [L], (1 << 31) + 4096: [H, L], n - 3: [L, H, H],
+              (1 << 30) + 1: [H]}
+    for p, pat in plants.items():
+        t[p:p + len(pat)] = torch.tensor(np.array(pat, np.uint16).view(np.int16), device="cuda")
+    out = torch.empty_like(t)
+    wf.utf16_to_well_formed(t, out)
+    assert not wf.is_well_formed(t)
+    loc = wf.utf16_locate_ill_formed(t).cpu().numpy()
+    host_windows = {}
+    for p in plants:
+        a, b = max(0, p - 64), min(n, p + 64)
+        host_windows[p] = (a, b, to_host(t[a:b]))
+    bad_units = set()
+    for p, (a, b, s) in sorted(host_windows.items()):
+        ctx_a, ctx_b = a - (1 if a > 0 else 0), b + (1 if b < n else 0)
+        s_ctx = to_host(t[ctx_a:ctx_b])
+        w = oracle.to_well_formed(s_ctx)[a - ctx_a:a - ctx_a + (b - a)]
+        assert_same(to_host(out[a:b]), w, f"window at {p}")
+        bad_units.update(a + int(i) for i in np.nonzero(w != s)[0])
+    assert len(bad_units) == 6
+    assert int(loc[1]) == len(bad_units) and int(loc[0]) == min(bad_units)
+    wf.utf16_to_well_formed_inplace(t)
+    for p, (a, b, s) in host_windows.items():
+        assert_same(to_host(t[a:b]), to_host(out[a:b]), f"in place window at {p}")
+    assert wf.is_well_formed(t)
+    # a batch whose offsets pass 2^31
+    t2 = out  # reuse: fill with a known pattern
+    t2.fill_(A)
+    t2[(1 << 31) - 2] = H - 65536
+    t2[(1 << 31) - 1] = L - 65536
+    cut = np.array([0, (1 << 31) - 1, (1 << 31) + 5, n], np.int64)
+    offs = torch.from_numpy(cut).cuda()
+    res = wf.utf16_is_well_formed_batch(t2, offs).cpu().numpy()
+    assert list(res) == [0, 0, 1]  # the pair is cut by the offset at 2^31 - 1
+    wf.utf16_to_well_formed_batch_inplace(t2, offs)
+    assert list(to_host(t2[(1 << 31) - 3:(1 << 31) + 1])) == [A, 0xFFFD, 0xFFFD, A]
+    del t, out, t2
+    torch.cuda.empty_cache()
