@@ -188,22 +188,28 @@ struct TileStarts {
     int64_t knext;  // first k with off[k] + shift >= th
     bool next;      // a string starts at unit th
     bool inner;     // a string starts in (tl, th)
+    bool any;       // a string starts in [tl, th) (the bitmap has a bit set)
 };
 
 // Marks the string starts in [tl, th) in the wave's bitmap (bit u - tl).
-// `cursor` is the first k with off[k] + shift >= tl.
+// `cursor` is the first k with off[k] + shift >= tl. The bitmap is cleared
+// only when the previous tile left bits in it (`dirty`), so tiles inside one
+// long string touch no LDS at all.
 template <int R>
 __device__ __forceinline__ TileStarts scan_starts(const int64_t *off, int64_t nstr, int64_t shift,
                                                   int64_t cursor, int64_t tl, int64_t th, uint32_t *bm,
-                                                  int lane) {
+                                                  int lane, bool &dirty) {
     constexpr int kWords = 16 * R;
+    if (dirty) {
 #pragma unroll
-    for (int i = 0; i < (kWords + 63) / 64; ++i) {
-        const int w = i * 64 + lane;
-        if (w < kWords)
-            bm[w] = 0u;
+        for (int i = 0; i < (kWords + 63) / 64; ++i) {
+            const int w = i * 64 + lane;
+            if (w < kWords)
+                bm[w] = 0u;
+        }
+        wave_lds_sync();
+        dirty = false;
     }
-    wave_lds_sync();
     int64_t k = cursor, le = 0;
     bool next = false, inner = false;
     for (;;) {
@@ -225,8 +231,12 @@ __device__ __forceinline__ TileStarts scan_starts(const int64_t *off, int64_t ns
         if (c < 64)
             break;
     }
-    wave_lds_sync();
-    return TileStarts{cursor + le - 1, k, next, inner};
+    const bool any = k != cursor;
+    if (any) {
+        wave_lds_sync();
+        dirty = true;
+    }
+    return TileStarts{cursor + le - 1, k, next, inner, any};
 }
 
 // ------------------------------------------------------------- the kernel
@@ -274,9 +284,11 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
         return;  // (flat locate waves without tiles still report to their workgroup)
 
     uint32_t *bm = BATCH ? s_bm + wslot * kWords : nullptr;
-    int64_t cursor = 0;
-    if constexpr (BATCH)
-        cursor = lower_bound_wave(off, a.nstr + 1, tb * T - shift, lane);
+    bool bm_dirty = true;  // LDS starts with arbitrary contents
+    // batch: first string index of the wave's first tile, searched after
+    // that tile's loads are in flight (before them only for OP_IS, whose
+    // early exit needs it first)
+    int64_t cursor = -1;
 
     // OP_LOCATE accumulators: count per lane, first index per wave. Flat:
     // the whole run; batch: consecutive tiles that lie inside one string
@@ -315,12 +327,14 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
         }
         const bool interior = tl >= lo && th <= hi;
         u32x4 v[R];
-        TileStarts ts{0, 0, false, false};
+        TileStarts ts{0, 0, false, false, false};
 
         if constexpr (BATCH && OP == kOpIs) {
             // Check first whether the whole tile lies in a string already
             // known to be ill-formed; then its data need not be read at all.
-            ts = scan_starts<R>(off, a.nstr, shift, cursor, tl, th, bm, lane);
+            if (cursor < 0)
+                cursor = lower_bound_wave(off, a.nstr + 1, tl - shift, lane);
+            ts = scan_starts<R>(off, a.nstr, shift, cursor, tl, th, bm, lane, bm_dirty);
             cursor = ts.knext;
             if (!ts.inner && ts.kc >= 0 && ts.kc < a.nstr &&
                 __hip_atomic_load(a.results + ts.kc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
@@ -337,7 +351,9 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
         if constexpr (OP == kOpIs && !BATCH)
             poll = __hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if constexpr (BATCH && OP != kOpIs) {
-            ts = scan_starts<R>(off, a.nstr, shift, cursor, tl, th, bm, lane);
+            if (cursor < 0)
+                cursor = lower_bound_wave(off, a.nstr + 1, tl - shift, lane);
+            ts = scan_starts<R>(off, a.nstr, shift, cursor, tl, th, bm, lane, bm_dirty);
             cursor = ts.knext;
         }
         // batch locate: does the whole tile lie inside one string?
@@ -350,23 +366,19 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
             }
         }
 
-        // classify every row; ballot the two flags neighbours need
-        uint32_t hA[R], hB[R], lA[R], lB[R], sA[R], sB[R];
+        // Phase 1: per row, ballot the two flags that neighbouring lanes
+        // need: "my unit 7 is high" and "my unit 0 is a low that may pair
+        // backwards" (not a string start). Only those two units are looked
+        // at here; each row is classified in full in phase 2, so no per-row
+        // flag arrays stay live across the phases (keeps the wave at full
+        // occupancy).
+        uint32_t sbits[R];
         uint64_t hl[R], lf[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            flags4(high_bytes(v[r].x, v[r].y), hA[r], lA[r]);
-            flags4(high_bytes(v[r].z, v[r].w), hB[r], lB[r]);
-            if constexpr (BATCH) {
-                const uint32_t sbits = reinterpret_cast<const uint8_t *>(bm)[r * 64 + lane];
-                sA[r] = spread4(sbits);
-                sB[r] = spread4(sbits >> 4);
-            } else {
-                sA[r] = 0u;
-                sB[r] = 0u;
-            }
-            hl[r] = __ballot((hB[r] >> 31) & 1u);               // unit 7 is high
-            lf[r] = __ballot(((lA[r] & ~sA[r]) >> 7) & 1u);     // unit 0 is a low that may pair back
+            sbits[r] = (BATCH && ts.any) ? (uint32_t)reinterpret_cast<const uint8_t *>(bm)[r * 64 + lane] : 0u;
+            hl[r] = __ballot(is_high_unit(v[r].w >> 16));
+            lf[r] = __ballot(is_low_unit(v[r].x & 0xFFFFu) && !(sbits[r] & 1u));
         }
 
         // one unit of context at each tile end, read only when it matters
@@ -382,14 +394,19 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
             const uint64_t nm = (lf[r] >> 1) | ((r == R - 1 ? carry_nx : (lf[r + 1] & 1ull)) << 63);
             const uint32_t hp = (uint32_t)(pm >> lane) & 1u;
             const uint32_t ln = (uint32_t)(nm >> lane) & 1u;
-            const uint32_t lAp = lA[r] & ~sA[r], lBp = lB[r] & ~sB[r];
+            // Phase 2: classify the row's 8 units
+            uint32_t hA, hB, lA, lB;
+            flags4(high_bytes(v[r].x, v[r].y), hA, lA);
+            flags4(high_bytes(v[r].z, v[r].w), hB, lB);
+            const uint32_t sA = spread4(sbits[r]), sB = spread4(sbits[r] >> 4);
+            const uint32_t lAp = lA & ~sA, lBp = lB & ~sB;
             // predecessor is high (cut at string starts) / successor is low
-            const uint32_t psA = ((hA[r] << 8) | (hp << 7)) & ~sA[r];
-            const uint32_t psB = ((hB[r] << 8) | (hA[r] >> 24)) & ~sB[r];
+            const uint32_t psA = ((hA << 8) | (hp << 7)) & ~sA;
+            const uint32_t psB = ((hB << 8) | (hA >> 24)) & ~sB;
             const uint32_t nsA = (lAp >> 8) | (lBp << 24);
             const uint32_t nsB = (lBp >> 8) | (ln << 31);
-            const uint32_t badA = (hA[r] & ~nsA) | (lA[r] & ~psA);
-            const uint32_t badB = (hB[r] & ~nsB) | (lB[r] & ~psB);
+            const uint32_t badA = (hA & ~nsA) | (lA & ~psA);
+            const uint32_t badB = (hB & ~nsB) | (lB & ~psB);
             const bool lane_bad = (badA | badB) != 0u;
             const uint64_t wave_bad = __ballot(lane_bad);
             const int64_t u0 = tl + ((int64_t)r * 64 + lane) * 8;

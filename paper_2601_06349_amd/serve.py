@@ -65,7 +65,7 @@ def simulate(arrival_ns, lengths, config: ServeConfig, lat_base_ns=20_000, lat_n
 def latency_summary(outcomes, arrival_ns, lengths):
     """p50 / p99 / mean / max latency (ms) of completed requests, from their
     scheduled arrival to the host seeing their batch complete; throughput in
-    GB/s of input over the run; GPU busy fraction (union of batch intervals)."""
+    GB/s of input over the run; fraction of the run with at least one batch in flight (launch to completion seen by the host)."""
     ok = outcomes["status"] == 0
     lat = (outcomes["done_ns"][ok] - np.asarray(arrival_ns)[ok]) / 1e6
     res = {"completed": int(ok.sum())}
@@ -88,7 +88,7 @@ def latency_summary(outcomes, arrival_ns, lengths):
                 cur_e = max(cur_e, e)
         if cur_e is not None:
             busy += cur_e - cur_s
-        res["busy_frac"] = round(float(busy) / max(t_end - t_start, 1.0), 4)
+        res["inflight_frac"] = round(float(busy) / max(t_end - t_start, 1.0), 4)
         res["batches"] = int(first.size)
         res["mean_batch_requests"] = round(float(ok.sum()) / max(first.size, 1), 2)
     return res

@@ -151,4 +151,4 @@ def test_latency_summary():
     out, st = S.simulate(arr, lens, cfg, lat_base_ns=500_000)
     s = S.latency_summary(out, arr, lens)
     assert s["completed"] == 10 and abs(s["p50_ms"] - 0.5) < 1e-6 and abs(s["p99_ms"] - 0.5) < 1e-6
-    assert 0.0 < s["busy_frac"] <= 1.0
+    assert 0.0 < s["inflight_frac"] <= 1.0
