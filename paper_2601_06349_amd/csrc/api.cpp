@@ -141,6 +141,7 @@ struct Workspace {
 };
 std::mutex g_ws_mu;
 Workspace g_ws[kMaxDevices];
+std::mutex g_validate_mu[kMaxDevices];
 
 int workspace(int dev, Workspace **ws) {
     std::lock_guard<std::mutex> lk(g_ws_mu);
@@ -268,8 +269,12 @@ int batch_call(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets
     const int64_t m = (int64_t)((addr(in) & 15u) >> 1);
     KernelArgs a{};
     a.in = in - m;
-    a.out = (op == kOpTo || op == kOpToInplace) ? (op == kOpToInplace ? const_cast<uint16_t *>(in) : out) - m
-                                                : nullptr;
+    uint16_t *dst = nullptr;
+    if (op == kOpTo)
+        dst = out;
+    else if (op == kOpToInplace)
+        dst = const_cast<uint16_t *>(in);
+    a.out = dst ? dst - m : nullptr;
     a.lo = 0;
     a.hi = 0;
     a.offsets = offsets;
@@ -404,6 +409,9 @@ int utf16wf_validate_offsets(const int64_t *offsets, int64_t num_strings, int64_
     Workspace *ws;
     if ((rc = workspace(dev, &ws)) != UTF16WF_OK)
         return rc;
+    // the device flag is shared by every validation on this device; the call
+    // is synchronous, so holding the lock for its duration serialises them
+    std::lock_guard<std::mutex> lk(g_validate_mu[dev]);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
     if ((e = launch_fill_i32(ws->flag, 0, 1, s)) != hipSuccess)

@@ -142,3 +142,40 @@ def test_product_path_has_no_cpu_route():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "utf16_oracle" not in text and "liboracle" not in text, f
+
+
+def test_tuning_cache_applies(tmp_path, L):
+    import json
+
+    import paper_2601_06349_amd as wf
+    from paper_2601_06349_amd import tune
+    path = tmp_path / "cache.json"
+    path.write_text(json.dumps({"entries": [
+        {"op": wf.OP_TO, "batch": 0, "size_class": 20,
+         "params": {"rows": 2, "wg_waves": 16, "grid_per_cu": 5, "nontemporal": 1}},
+        {"op": wf.OP_IS, "batch": 1, "size_class": 40,
+         "params": {"rows": 8, "wg_waves": 1, "grid_per_cu": 64, "nontemporal": 0}}]}))
+    wf.reset_params()
+    try:
+        assert tune.apply_cache(str(path)) == "cache.json"
+        assert wf.get_params(wf.OP_TO, 0, 1 << 20) == {"rows": 2, "wg_waves": 16, "grid_per_cu": 5,
+                                                      "nontemporal": 1}
+        assert wf.get_params(wf.OP_IS, 1, 1 << 40)["grid_per_cu"] == 64
+        assert wf.get_params(wf.OP_TO, 0, 1 << 21) != wf.get_params(wf.OP_TO, 0, 1 << 20)
+    finally:
+        wf.reset_params()
+
+
+def test_committed_tuning_cache_is_valid():
+    """Every entry of the committed cache names a valid key and shape."""
+    import json
+    d = os.path.join(ROOT, "paper_2601_06349_amd", "tuning")
+    files = [f for f in os.listdir(d) if f.endswith(".json")]
+    assert files
+    for f in files:
+        data = json.load(open(os.path.join(d, f)))
+        for e in data["entries"]:
+            p = e["params"]
+            assert e["op"] in (0, 1, 2, 3) and e["batch"] in (0, 1) and 0 <= e["size_class"] <= 40
+            assert p["rows"] in (1, 2, 4, 8) and 1 <= p["wg_waves"] <= 16 and 1 <= p["grid_per_cu"] <= 64
+            assert e["tuned_ms"] <= e["default_ms"] * 1.0001

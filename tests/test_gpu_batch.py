@@ -190,17 +190,24 @@ def test_validate_offsets(wf):
 
 
 def test_ragged_1m_full(wf):
-    """1,000,000 log-normal strings (about 98.6M units), default shape."""
+    """1,000,000 log-normal strings (about 98.6M units), with the tuned
+    launch shapes the benchmark uses, launched with and without a size hint."""
+    from paper_2601_06349_amd import tune
+    tune.apply_cache()
     log("generating ragged_1m")
     buf, off = W.ragged_batch()
     log(f"ragged_1m: {off.size - 1} strings, {off[-1]} units")
     _check_batch(wf, buf, off, what="ragged_1m")
+    _check_batch(wf, buf, off, what="ragged_1m hinted", hint=int(off[-1]))
+    wf.reset_params()
 
 
 def test_zipf_4096_full(wf):
     """4096 Zipf(1.1) strings up to 2^24 units (about 1.6G units), default
     shape: out of place, in place, is (early exit), locate."""
     torch = torch_mod()
+    from paper_2601_06349_amd import tune
+    tune.apply_cache()
     log("generating zipf_4096")
     buf, off, kind = W.zipf_batch()
     log(f"zipf_4096: {off[-1]} units, {int(kind.sum())} error strings")
@@ -219,3 +226,4 @@ def test_zipf_4096_full(wf):
     assert_same(to_host(t_in), want, "zipf inplace")
     del t_in
     torch.cuda.empty_cache()
+    wf.reset_params()

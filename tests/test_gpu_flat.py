@@ -173,6 +173,8 @@ def test_single_buffer_full_size(wf, variant):
     """The 268,435,456-unit buffers at full size, default launch shape (the
     one the benchmark times): out of place, in place, is, locate."""
     torch = torch_mod()
+    from paper_2601_06349_amd import tune
+    tune.apply_cache()  # the launch shapes the benchmark uses
     log(f"generating {variant}")
     s = W.single_buffer(variant)
     want, cnt = oracle.to_well_formed_count(s)
@@ -191,6 +193,7 @@ def test_single_buffer_full_size(wf, variant):
         assert abs(cnt / s.size - 0.5) < 0.01  # about half of the units pair up
     del t_in, t_out
     torch.cuda.empty_cache()
+    wf.reset_params()
 
 
 def test_beyond_32bit_indices(wf):
