@@ -424,6 +424,8 @@ def main():
                               arena_bytes=64 << 30, log=log)
         ex["serve"] = sv
         result["serve_p99_ms"] = sv.get("p99_ms")
+        log("extras: the paper's 1024-unit strings, served")
+        ex["paper_workloads"]["js_1024_served"] = S.serve_js_strings(duration_s=1.0, rate_hz=1_000_000, log=log)
         result["extras"] = ex
 
     print(json.dumps(result), flush=True)

@@ -574,27 +574,64 @@ __global__ void validate_kernel(const int64_t *off, int64_t nstr, int64_t buf_un
     }
 }
 
-// Copies each chunk (one workgroup per chunk): 16-byte accesses when source
-// and destination share their alignment modulo 16, else unit by unit.
+// 16 bytes starting `sh` bytes (even, 2..14) into the 32 bytes a|b.
+__device__ __forceinline__ u32x4 realign(u32x4 a, u32x4 b, uint32_t sh) {
+    const uint32_t k = sh & 3u;  // 0 or 2: byte shift inside a dword
+    u32x4 o;
+    switch (sh >> 2) {
+    case 0:
+        o = (u32x4){__builtin_amdgcn_alignbyte(a.y, a.x, k), __builtin_amdgcn_alignbyte(a.z, a.y, k),
+                    __builtin_amdgcn_alignbyte(a.w, a.z, k), __builtin_amdgcn_alignbyte(b.x, a.w, k)};
+        break;
+    case 1:
+        o = (u32x4){__builtin_amdgcn_alignbyte(a.z, a.y, k), __builtin_amdgcn_alignbyte(a.w, a.z, k),
+                    __builtin_amdgcn_alignbyte(b.x, a.w, k), __builtin_amdgcn_alignbyte(b.y, b.x, k)};
+        break;
+    case 2:
+        o = (u32x4){__builtin_amdgcn_alignbyte(a.w, a.z, k), __builtin_amdgcn_alignbyte(b.x, a.w, k),
+                    __builtin_amdgcn_alignbyte(b.y, b.x, k), __builtin_amdgcn_alignbyte(b.z, b.y, k)};
+        break;
+    default:
+        o = (u32x4){__builtin_amdgcn_alignbyte(b.x, a.w, k), __builtin_amdgcn_alignbyte(b.y, b.x, k),
+                    __builtin_amdgcn_alignbyte(b.z, b.y, k), __builtin_amdgcn_alignbyte(b.w, b.z, k)};
+        break;
+    }
+    return o;
+}
+
+// Copies each chunk (one workgroup per chunk) with 16-byte stores: after a
+// head that aligns the destination, each 16-byte destination vector is built
+// from the two aligned 16-byte source vectors it straddles (when source and
+// destination alignments differ) or copied straight (when they agree). Only
+// the last vector and the tail go unit by unit, so no source byte past the
+// chunk is ever read.
 __global__ void __launch_bounds__(256) chunk_copy_kernel(const CopyChunk *chunks) {
     const CopyChunk c = chunks[blockIdx.x];
     const int64_t n = c.n;
     const uintptr_t sa = reinterpret_cast<uintptr_t>(c.src), da = reinterpret_cast<uintptr_t>(c.dst);
-    if (((sa ^ da) & 15u) == 0 && n >= 64) {
-        const int64_t head = min(n, (int64_t)(((16u - (da & 15u)) & 15u) >> 1));
-        if (threadIdx.x < head)
-            c.dst[threadIdx.x] = c.src[threadIdx.x];
-        const int64_t nv = (n - head) >> 3;
+    const int64_t head = min(n, (int64_t)(((16u - (da & 15u)) & 15u) >> 1));
+    if (threadIdx.x < head)
+        c.dst[threadIdx.x] = c.src[threadIdx.x];
+    const int64_t nv = (n - head) >> 3;  // whole destination vectors
+    u32x4 *d4 = reinterpret_cast<u32x4 *>(c.dst + head);
+    int64_t done = head;                 // units [0, done) handled by the vector loops
+    if (((sa ^ da) & 15u) == 0) {
         const u32x4 *s4 = reinterpret_cast<const u32x4 *>(c.src + head);
-        u32x4 *d4 = reinterpret_cast<u32x4 *>(c.dst + head);
         for (int64_t i = threadIdx.x; i < nv; i += blockDim.x)
             d4[i] = s4[i];
-        for (int64_t i = head + nv * 8 + threadIdx.x; i < n; i += blockDim.x)
-            c.dst[i] = c.src[i];
-    } else {
-        for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
-            c.dst[i] = c.src[i];
+        done = head + nv * 8;
+    } else if (nv >= 2) {
+        const uintptr_t s0 = sa + 2 * (uintptr_t)head;
+        const u32x4 *sv = reinterpret_cast<const u32x4 *>(s0 & ~(uintptr_t)15);
+        const uint32_t sh = (uint32_t)(s0 & 15u);
+        // vector i reads source vectors i and i+1; for i <= nv - 2 both end
+        // at or before the source byte of unit head + 8 * nv <= n
+        for (int64_t i = threadIdx.x; i < nv - 1; i += blockDim.x)
+            d4[i] = realign(sv[i], sv[i + 1], sh);
+        done = head + (nv - 1) * 8;
     }
+    for (int64_t i = done + threadIdx.x; i < n; i += blockDim.x)
+        c.dst[i] = c.src[i];
 }
 
 template <typename T>

@@ -125,3 +125,35 @@ def serve_workload(duration_s=5.0, rate_hz=50_000.0, num_streams=4, arena_bytes=
                  "num_streams": num_streams, "arena_bytes": arena_bytes, "stats": st})
     del d_pools
     return summ
+
+
+def serve_js_strings(duration_s=1.0, rate_hz=1_000_000.0, num_streams=4, arena_bytes=1 << 30,
+                     max_batch_requests=65536, n_distinct=4096, seed=1601, log=None):
+    """The paper's JavaScript shape served: Poisson arrivals of 1024-unit
+    strings with 5 % lone lows and 5 % lone highs (the rest ASCII), each a
+    copy of one of ``n_distinct`` device-resident strings. Returns a summary
+    dict."""
+    import torch
+
+    from . import workloads as W
+    rng = np.random.default_rng(seed)
+    pool = np.concatenate([W.js_string(seed=rng) for _ in range(n_distinct)])
+    d_pool = torch.from_numpy(pool.view(np.int16)).cuda()
+    count = int(rng.poisson(rate_hz * duration_s))
+    arrival = (np.cumsum(rng.exponential(1.0 / rate_hz, size=count)) * 1e9).astype(np.int64)
+    which = rng.integers(0, n_distinct, size=count)
+    reqs = np.zeros(count, dtype=REQUEST_DTYPE)
+    reqs["arrival_ns"] = arrival
+    reqs["src"] = np.uint64(d_pool.data_ptr()) + (2 * 1024 * which).astype(np.uint64)
+    reqs["length"] = 1024
+    if log:
+        log(f"serve js: {count} requests of 1024 units at {rate_hz:.0f}/s")
+    torch.cuda.synchronize()
+    cfg = make_config(num_streams=num_streams, op=OP_TO, arena_bytes=arena_bytes,
+                      max_batch_requests=max_batch_requests, max_batch_units=1 << 26)
+    out, st = run(reqs, cfg)
+    summ = latency_summary(out, arrival, reqs["length"])
+    summ.update({"requests": count, "duration_s": duration_s, "rate_hz": rate_hz, "num_streams": num_streams,
+                 "stats": st})
+    del d_pool
+    return summ
