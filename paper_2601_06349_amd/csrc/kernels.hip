@@ -285,10 +285,17 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
 
     uint32_t *bm = BATCH ? s_bm + wslot * kWords : nullptr;
     bool bm_dirty = true;  // LDS starts with arbitrary contents
-    // batch: first string index of the wave's first tile, searched after
-    // that tile's loads are in flight (before them only for OP_IS, whose
-    // early exit needs it first)
+    // batch: first string index of the wave's first tile. With many strings
+    // the search is long and its result gates the tile's offsets scan, so it
+    // runs first and the scan's loads then overlap the data loads; with few
+    // (long) strings it is short and runs after the first tile's loads are
+    // in flight. OP_IS always searches first (its skip test needs it before
+    // any load). Measured on the 1M-string and 4096-string batches.
     int64_t cursor = -1;
+    if constexpr (BATCH) {
+        if (a.nstr > 65536)
+            cursor = lower_bound_wave(off, a.nstr + 1, tb * T - shift, lane);
+    }
 
     // OP_LOCATE accumulators: count per lane, first index per wave. Flat:
     // the whole run; batch: consecutive tiles that lie inside one string
@@ -366,19 +373,20 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
             }
         }
 
-        // Phase 1: per row, ballot the two flags that neighbouring lanes
-        // need: "my unit 7 is high" and "my unit 0 is a low that may pair
-        // backwards" (not a string start). Only those two units are looked
-        // at here; each row is classified in full in phase 2, so no per-row
-        // flag arrays stay live across the phases (keeps the wave at full
-        // occupancy).
-        uint32_t sbits[R];
+        // Phase 1: classify every row and ballot the two flags that
+        // neighbouring lanes need: "my unit 7 is high" and "my unit 0 is a
+        // low that may pair backwards" (not a string start). (Keeping the
+        // flags live into phase 2 costs occupancy in the batch kernel but
+        // measured faster than classifying again there.)
+        uint32_t hA_[R], hB_[R], lA_[R], lB_[R], sbits[R];
         uint64_t hl[R], lf[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
+            flags4(high_bytes(v[r].x, v[r].y), hA_[r], lA_[r]);
+            flags4(high_bytes(v[r].z, v[r].w), hB_[r], lB_[r]);
             sbits[r] = (BATCH && ts.any) ? (uint32_t)reinterpret_cast<const uint8_t *>(bm)[r * 64 + lane] : 0u;
-            hl[r] = __ballot(is_high_unit(v[r].w >> 16));
-            lf[r] = __ballot(is_low_unit(v[r].x & 0xFFFFu) && !(sbits[r] & 1u));
+            hl[r] = __ballot((hB_[r] >> 31) & 1u);
+            lf[r] = __ballot(((lA_[r] & ~spread4(sbits[r])) >> 7) & 1u);
         }
 
         // one unit of context at each tile end, read only when it matters
@@ -394,10 +402,8 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
             const uint64_t nm = (lf[r] >> 1) | ((r == R - 1 ? carry_nx : (lf[r + 1] & 1ull)) << 63);
             const uint32_t hp = (uint32_t)(pm >> lane) & 1u;
             const uint32_t ln = (uint32_t)(nm >> lane) & 1u;
-            // Phase 2: classify the row's 8 units
-            uint32_t hA, hB, lA, lB;
-            flags4(high_bytes(v[r].x, v[r].y), hA, lA);
-            flags4(high_bytes(v[r].z, v[r].w), hB, lB);
+            // Phase 2: mismatches of the row's 8 units
+            const uint32_t hA = hA_[r], hB = hB_[r], lA = lA_[r], lB = lB_[r];
             const uint32_t sA = spread4(sbits[r]), sB = spread4(sbits[r] >> 4);
             const uint32_t lAp = lA & ~sA, lBp = lB & ~sB;
             // predecessor is high (cut at string starts) / successor is low

@@ -3,8 +3,9 @@
 For each (operation, flat or batch, size class) it times every launch shape
 in a grid — 16-byte loads per lane per tile (rows), waves per workgroup,
 workgroups per compute unit, streaming cache hints — with HIP events on
-synthetic inputs of that size (for the flat operations, summed over several
-kinds of content: clean text, text with lone surrogates, all surrogates),
+synthetic inputs of that size (for the flat operations, summed over the five
+kinds of content of the single-buffer workload, launched in turn, each into
+its own output),
 re-times the best few with more repetitions, and keeps the fastest. The
 untuned default is timed beside it and both are written to the cache, so the
 gain is visible.
@@ -146,43 +147,44 @@ def tune(quick=False, flat_classes=None, out=None, log=print):
     flat_classes = flat_classes or (list(range(10, 29, 2)) if quick else list(range(10, 29)))
     names = {wf.OP_IS: "is", wf.OP_TO: "to", wf.OP_TO_INPLACE: "to_inplace", wf.OP_LOCATE: "locate"}
     t_start = time.time()
-    # Representative inputs: the character mix with lone surrogates (errors
-    # in most tiles), the clean mix, and all units surrogates (every tile edge
-    # needs its context unit). A shape is scored on the sum over them, so it
-    # is not tuned to one kind of content.
+    # Representative inputs: the five kinds of content of the single-buffer
+    # workload (pure ASCII, the character mix at lone-surrogate rates 0, 1e-6
+    # and 1e-2, all units surrogates), drawn with other seeds, each copy
+    # written to its own output. A shape is scored on the sum over them, so
+    # it is tuned neither to one kind of content nor to a re-written buffer.
     top = 1 << max(flat_classes)
-    d_mix = torch.from_numpy(W.mix(top, 1e-3, 4242).view(np.int16)).cuda()
-    d_clean = torch.from_numpy(W.mix(top, 0.0, 4243).view(np.int16)).cuda()
-    d_sur = torch.from_numpy(W.all_surrogates(top, 4244).view(np.int16)).cuda()
-    d_ascii = torch.from_numpy(W.ascii_units(top, 4245).view(np.int16)).cuda()
-    d_outs = [torch.empty_like(d_mix) for _ in range(3)]  # one output per input: no re-written buffer
-    d_tmp = torch.empty_like(d_mix)
-    d_tmp2 = torch.empty_like(d_mix)
+    kinds = W.SINGLE_VARIANTS
+    d_in = {v: torch.from_numpy(W.single_buffer(v, n=top, seed=4242 + i).view(np.int16)).cuda()
+            for i, v in enumerate(kinds)}
+    d_outs = [torch.empty_like(d_in[kinds[0]]) for _ in kinds]
+    d_tmp = [torch.empty_like(d_in[kinds[0]]) for _ in range(2)]
     res = torch.empty(4, dtype=torch.int64, device="cuda")
     for c in flat_classes:
         n = 1 << c
         reps = 10 if n >= 1 << 24 else 15
-        x, s_, z, z2, cl, asc = d_mix[:n], d_sur[:n], d_tmp[:n], d_tmp2[:n], d_clean[:n], d_ascii[:n]
-        y1, y2, y3 = (o[:n] for o in d_outs)
-        z.copy_(x)
-        z2.copy_(asc)
+        x = {v: d_in[v][:n] for v in kinds}
+        ys = [o[:n] for o in d_outs]
+        z1, z2 = d_tmp[0][:n], d_tmp[1][:n]
+        z1.copy_(x["mix1e-2"])
+        z2.copy_(x["ascii"])
         r32 = res[:1].view(torch.int32)
         calls = {
-            wf.OP_TO: [lambda: wf.utf16_to_well_formed(x, y1), lambda: wf.utf16_to_well_formed(cl, y2),
-                       lambda: wf.utf16_to_well_formed(s_, y3)],
+            wf.OP_TO: [(lambda a=x[v], b=ys[i]: wf.utf16_to_well_formed(a, b)) for i, v in enumerate(kinds)],
             # in place: after its first call a buffer is clean (the common case)
-            wf.OP_TO_INPLACE: [lambda: wf.utf16_to_well_formed_inplace(z),
+            wf.OP_TO_INPLACE: [lambda: wf.utf16_to_well_formed_inplace(z1),
                                lambda: wf.utf16_to_well_formed_inplace(z2)],
             # isWellFormed: full passes over clean inputs (errors end it early)
-            wf.OP_IS: [lambda: wf.utf16_is_well_formed(cl, r32), lambda: wf.utf16_is_well_formed(asc, r32)],
-            wf.OP_LOCATE: [lambda: wf.utf16_locate_ill_formed(x), lambda: wf.utf16_locate_ill_formed(cl)],
+            wf.OP_IS: [lambda: wf.utf16_is_well_formed(x["mix0"], r32),
+                       lambda: wf.utf16_is_well_formed(x["ascii"], r32)],
+            wf.OP_LOCATE: [lambda: wf.utf16_locate_ill_formed(x["mix1e-2"]),
+                           lambda: wf.utf16_locate_ill_formed(x["mix0"])],
         }
         for op, cs in calls.items():
             params, ms, dms = _sweep(wf, run, op, 0, c, cs, reps, quick)
             entries.append({"op": op, "op_name": names[op], "batch": 0, "size_class": c, "params": params,
                             "tuned_ms": round(ms, 5), "default_ms": round(dms, 5), "inputs": len(cs)})
             log(f"flat {names[op]:10s} 2^{c:2d}: tuned {ms * 1e3:9.1f} us  default {dms * 1e3:9.1f} us  {params}")
-    del d_mix, d_clean, d_sur, d_ascii, d_outs, d_tmp, d_tmp2
+    del d_in, d_outs, d_tmp
 
     # batches: the Zipf(1.1) 4096-string workload (launched without a size
     # hint, so it sets the parameters for unknown sizes) and the 1,000,000
