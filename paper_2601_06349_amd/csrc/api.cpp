@@ -285,6 +285,13 @@ int batch_call(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets
     a.first = first;
     a.count = count;
     a.scalar_store = (op == kOpTo && (addr(out) & 15u) != (addr(in) & 15u)) ? 1 : 0;
+    // few long strings (or an unknown total): check each string's head first
+    // so the main pass can skip strings whose first mismatch lies near their
+    // start
+    if (op == kOpIs && nstr <= 65536 && (units_hint == 0 || units_hint / nstr >= 8192)) {
+        if ((e = launch_head_check(a.in, offsets, nstr, m, results, stream)) != hipSuccess)
+            return hip_fail(e, "head check launch");
+    }
     const utf16wf_params p = get_params(op, 1, units_hint > 0 ? units_hint : (int64_t)1 << 40);
     const LaunchShape sh = make_shape(p, cus, units_hint, 0);
     if ((e = launch_main(op, true, sh, a, stream)) != hipSuccess)

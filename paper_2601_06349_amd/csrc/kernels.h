@@ -57,6 +57,11 @@ struct CopyChunk {
 constexpr int64_t kCopyChunkUnits = 16384;
 hipError_t launch_chunk_copy(const CopyChunk *chunks, int64_t nchunks, hipStream_t stream);
 
+// Batch isWellFormed of few long strings: clears the result of every
+// string of at least 8192 units with a mismatch among its first 512 units.
+hipError_t launch_head_check(const uint16_t *in_frame, const int64_t *offsets, int64_t nstr, int64_t shift,
+                             uint8_t *results, hipStream_t stream);
+
 hipError_t launch_validate(const int64_t *offsets, int64_t nstr, int64_t buf_units, int32_t *bad,
                            hipStream_t stream);
 

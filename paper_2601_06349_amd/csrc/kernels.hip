@@ -344,8 +344,16 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
             ts = scan_starts<R>(off, a.nstr, shift, cursor, tl, th, bm, lane, bm_dirty);
             cursor = ts.knext;
             if (!ts.inner && ts.kc >= 0 && ts.kc < a.nstr &&
-                __hip_atomic_load(a.results + ts.kc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+                __hip_atomic_load(a.results + ts.kc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                // jump to the tile where string kc ends: the tiles before it
+                // lie inside kc and need neither a scan nor a load
+                const int64_t tn = (off[ts.kc + 1] + shift) / T;
+                if (tn > t + 1) {
+                    t = tn - 1;
+                    cursor = ts.kc + 1;  // off[kc] < tn * T <= off[kc + 1]
+                }
                 continue;
+            }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -452,6 +460,17 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
                         }
                         return;
                     }
+                } else if (single) {
+                    // The whole tile is string kc: one store settles it (and
+                    // none if another wave already did), and the tile's
+                    // remaining rows have nothing left to decide.
+                    if (wave_bad) {
+                        if (lane == 0 && __hip_atomic_load(a.results + ts.kc, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT) != 0)
+                            __hip_atomic_store(a.results + ts.kc, (uint8_t)0, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
                 } else {
                     if (lane_bad) {
                         uint64_t m = bad64;
@@ -525,6 +544,44 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
             }
         }
     }
+}
+
+// isWellFormed of a batch of few, long strings: one wave per string checks
+// the string's first 512 units (with the unit after them as context) and
+// clears the string's result when one of them is mismatched. Launched before
+// the main pass, it lets that pass skip every tile of a string whose first
+// mismatch lies near its start, which it cannot learn in time on its own: the
+// tiles of one string are all in flight together. Strings shorter than
+// kHeadMinUnits are left to the main pass.
+constexpr int64_t kHeadMinUnits = 8192;
+__global__ void __launch_bounds__(256) head_check_kernel(const uint16_t *in, const int64_t *off, int64_t nstr,
+                                                         int64_t shift, uint8_t *results) {
+    const int lane = __lane_id();
+    const int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (k >= nstr)
+        return;
+    const int64_t s0 = off[k] + shift, s1 = off[k + 1] + shift;
+    if (s1 - s0 < kHeadMinUnits)
+        return;
+    const int64_t hend = s0 + kRowUnits;  // s1 > hend: the head lies inside the string
+    const u32x4 v = ld_partial(in, s0 + (int64_t)lane * 8, s0, hend);
+    uint32_t hA, hB, lA, lB;
+    flags4(high_bytes(v.x, v.y), hA, lA);
+    flags4(high_bytes(v.z, v.w), hB, lB);
+    const uint64_t hl = __ballot((hB >> 31) & 1u);
+    const uint64_t lf = __ballot((lA >> 7) & 1u);
+    const uint64_t carry_nx = is_low_unit(in[hend]) ? 1ull : 0ull;  // context only
+    const uint32_t hp = (uint32_t)((hl << 1) >> lane) & 1u;  // nothing precedes the string
+    const uint32_t ln = (uint32_t)(((lf >> 1) | (carry_nx << 63)) >> lane) & 1u;
+    const uint32_t sA = lane == 0 ? 0x80u : 0u;  // unit s0 starts the string
+    const uint32_t lAp = lA & ~sA;
+    const uint32_t psA = ((hA << 8) | (hp << 7)) & ~sA;
+    const uint32_t psB = (hB << 8) | (hA >> 24);
+    const uint32_t nsA = (lAp >> 8) | (lB << 24);
+    const uint32_t nsB = (lB >> 8) | (ln << 31);
+    const uint32_t bad = ((hA & ~nsA) | (lA & ~psA)) | ((hB & ~nsB) | (lB & ~psB));
+    if (__ballot(bad != 0u) && lane == 0)
+        __hip_atomic_store(results + k, (uint8_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Plain copy with the same tiling: the bandwidth ceiling for the repair.
@@ -718,6 +775,16 @@ hipError_t launch_chunk_copy(const CopyChunk *chunks, int64_t nchunks, hipStream
     if (nchunks <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(chunk_copy_kernel, dim3((unsigned)nchunks), dim3(256), 0, s, chunks);
+    return hipGetLastError();
+}
+
+hipError_t launch_head_check(const uint16_t *in_frame, const int64_t *offsets, int64_t nstr, int64_t shift,
+                             uint8_t *results, hipStream_t s) {
+    if (nstr <= 0)
+        return hipSuccess;
+    const int64_t blocks = (nstr + 3) / 4;
+    hipLaunchKernelGGL(head_check_kernel, dim3((unsigned)blocks), dim3(256), 0, s, in_frame, offsets, nstr, shift,
+                       results);
     return hipGetLastError();
 }
 

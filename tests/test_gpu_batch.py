@@ -227,3 +227,28 @@ def test_zipf_4096_full(wf):
     del t_in
     torch.cuda.empty_cache()
     wf.reset_params()
+
+
+def test_head_check_boundaries(wf):
+    """Batches of few long strings get a head check of each string's first
+    512 units: a pair across unit 511/512 is valid, a lone high at 511 is not,
+    strings just under and at the 8192-unit threshold, mismatches just past
+    the head."""
+    cases = []  # (length, {position: unit})
+    cases.append((8192, {511: H, 512: L}))        # valid pair across the head edge
+    cases.append((8192, {511: H}))                # lone high at the head's last unit
+    cases.append((8191, {0: L}))                  # below the threshold: main pass only
+    cases.append((8192, {0: L}))
+    cases.append((10000, {512: L}))               # first mismatch just past the head
+    cases.append((9000, {}))                      # well-formed
+    cases.append((20000, {510: H, 511: L, 19999: H}))
+    lens = np.array([c[0] for c in cases], np.int64)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    buf = np.full(int(off[-1]), A, np.uint16)
+    for k, (_, plants) in enumerate(cases):
+        for p, u in plants.items():
+            buf[off[k] + p] = u
+    for hint in (0, int(off[-1])):
+        _check_batch(wf, buf, off, what=f"head check hint={hint}", hint=hint)
+    for phase in (1, 6):
+        _check_batch(wf, buf, off, phase, phase, what=f"head check phase {phase}")
