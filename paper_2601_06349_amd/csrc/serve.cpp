@@ -3,8 +3,9 @@
 // simulated executor with a virtual clock.
 //
 // HIP executor, per batch on its slot's stream (default priority):
-//   1. offsets of the packed batch (H2D from pinned host memory, into the
-//      batch's arena region) and the gather descriptors (H2D);
+//   1. the batch's offsets and its gather / scatter descriptors, packed
+//      together, in one copy from pinned host memory to the slot's device
+//      staging buffer;
 //   2. gather: each request's payload is copied into the packed input;
 //   3. one batch launch (utf16wf_batch) repairs into the packed output, or
 //      checks into per-string results;
@@ -74,12 +75,12 @@ class HipExec {
                 return fail(e, "hipStreamCreateWithFlags");
             if ((e = hipEventCreateWithFlags(&sl.event, hipEventDisableTiming)) != hipSuccess)
                 return fail(e, "hipEventCreateWithFlags");
-            if ((e = hipHostMalloc((void **)&sl.h_off, 8 * (max_req_ + 1), 0)) != hipSuccess ||
-                (e = hipHostMalloc((void **)&sl.h_chunks, 2 * sizeof(CopyChunk) * max_chunks_, 0)) != hipSuccess ||
+            const size_t stage = 8 * (size_t)(max_req_ + 1) + 2 * sizeof(CopyChunk) * (size_t)max_chunks_;
+            if ((e = hipHostMalloc((void **)&sl.h_stage, stage, 0)) != hipSuccess ||
                 (e = hipHostMalloc((void **)&sl.h_res, max_req_ + 1, 0)) != hipSuccess)
                 return fail(e, "hipHostMalloc");
-            if ((e = hipMalloc((void **)&sl.d_chunks, 2 * sizeof(CopyChunk) * max_chunks_)) != hipSuccess)
-                return fail(e, "hipMalloc(chunks)");
+            if ((e = hipMalloc((void **)&sl.d_stage, stage)) != hipSuccess)
+                return fail(e, "hipMalloc(staging)");
         }
         t0_ = std::chrono::steady_clock::now();
         return UTF16WF_OK;
@@ -95,14 +96,12 @@ class HipExec {
                 (void)hipEventDestroy(sl.event);
             if (sl.stream)
                 (void)hipStreamDestroy(sl.stream);
-            if (sl.h_off)
-                (void)hipHostFree(sl.h_off);
-            if (sl.h_chunks)
-                (void)hipHostFree(sl.h_chunks);
+            if (sl.h_stage)
+                (void)hipHostFree(sl.h_stage);
             if (sl.h_res)
                 (void)hipHostFree(sl.h_res);
-            if (sl.d_chunks)
-                (void)hipFree(sl.d_chunks);
+            if (sl.d_stage)
+                (void)hipFree(sl.d_stage);
         }
         if (arena_)
             (void)hipFree(arena_);
@@ -117,34 +116,42 @@ class HipExec {
         uint8_t *base = static_cast<uint8_t *>(arena_) + b.region;
         uint16_t *d_in = reinterpret_cast<uint16_t *>(base + b.lay.in_off);
         uint16_t *d_out = reinterpret_cast<uint16_t *>(base + b.lay.out_off);
-        int64_t *d_offs = reinterpret_cast<int64_t *>(base + b.lay.offsets_off);
         uint8_t *d_res = base + b.lay.results_off;
         const int64_t nb = (int64_t)b.reqs.size();
-        int64_t g = 0, sc = 0, pos = 0;
-        CopyChunk *gat = sl.h_chunks, *sca = sl.h_chunks + max_chunks_;
-        sl.h_off[0] = 0;
+        // count the copy pieces first, so offsets, gather and scatter
+        // descriptors lie back to back in the staging buffer
+        int64_t g = 0, sc = 0;
+        for (int64_t i = 0; i < nb; ++i) {
+            const utf16wf_serve_request &r = reqs_[b.reqs[i]];
+            const int64_t pieces = (r.length + kCopyChunkUnits - 1) / kCopyChunkUnits;
+            g += pieces;
+            if (r.dst && cfg_.op == UTF16WF_OP_TO)
+                sc += pieces;
+        }
+        int64_t *h_off = reinterpret_cast<int64_t *>(sl.h_stage);
+        CopyChunk *gat = reinterpret_cast<CopyChunk *>(sl.h_stage + 8 * (nb + 1));
+        CopyChunk *sca = gat + g;
+        int64_t gi = 0, si = 0, pos = 0;
+        h_off[0] = 0;
         for (int64_t i = 0; i < nb; ++i) {
             const utf16wf_serve_request &r = reqs_[b.reqs[i]];
             for (int64_t c = 0; c < r.length; c += kCopyChunkUnits) {
                 const int64_t len = std::min(kCopyChunkUnits, r.length - c);
-                gat[g++] = CopyChunk{r.src + c, d_in + pos + c, len};
+                gat[gi++] = CopyChunk{r.src + c, d_in + pos + c, len};
                 if (r.dst && cfg_.op == UTF16WF_OP_TO)
-                    sca[sc++] = CopyChunk{d_out + pos + c, r.dst + c, len};
+                    sca[si++] = CopyChunk{d_out + pos + c, r.dst + c, len};
             }
             pos += r.length;
-            sl.h_off[i + 1] = pos;
+            h_off[i + 1] = pos;
         }
+        const size_t stage_bytes = 8 * (size_t)(nb + 1) + sizeof(CopyChunk) * (size_t)(g + sc);
+        const int64_t *d_offs = reinterpret_cast<const int64_t *>(sl.d_stage);
+        const CopyChunk *d_gat = reinterpret_cast<const CopyChunk *>(sl.d_stage + 8 * (nb + 1));
         hipStream_t st = sl.stream;
         hipError_t e;
-        if ((e = hipMemcpyAsync(d_offs, sl.h_off, 8 * (nb + 1), hipMemcpyHostToDevice, st)) != hipSuccess)
-            return fail(e, "copy offsets");
-        if (g > 0 && (e = hipMemcpyAsync(sl.d_chunks, gat, sizeof(CopyChunk) * g, hipMemcpyHostToDevice, st)) !=
-                         hipSuccess)
-            return fail(e, "copy gather descriptors");
-        if (sc > 0 && (e = hipMemcpyAsync(sl.d_chunks + max_chunks_, sca, sizeof(CopyChunk) * sc,
-                                          hipMemcpyHostToDevice, st)) != hipSuccess)
-            return fail(e, "copy scatter descriptors");
-        if ((e = launch_chunk_copy(sl.d_chunks, g, st)) != hipSuccess)
+        if ((e = hipMemcpyAsync(sl.d_stage, sl.h_stage, stage_bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
+            return fail(e, "copy offsets and descriptors");
+        if ((e = launch_chunk_copy(d_gat, g, st)) != hipSuccess)
             return fail(e, "gather");
         int rc;
         if (cfg_.op == UTF16WF_OP_TO)
@@ -153,7 +160,7 @@ class HipExec {
             rc = utf16wf_batch(UTF16WF_OP_IS, d_in, nullptr, d_offs, nb, d_res, nullptr, nullptr, pos, st);
         if (rc != UTF16WF_OK)
             return rc;
-        if (sc > 0 && (e = launch_chunk_copy(sl.d_chunks + max_chunks_, sc, st)) != hipSuccess)
+        if (sc > 0 && (e = launch_chunk_copy(d_gat + g, sc, st)) != hipSuccess)
             return fail(e, "scatter");
         if (cfg_.op == UTF16WF_OP_IS &&
             (e = hipMemcpyAsync(sl.h_res, d_res, nb, hipMemcpyDeviceToHost, st)) != hipSuccess)
@@ -197,10 +204,9 @@ class HipExec {
     struct Slot {
         hipStream_t stream = nullptr;
         hipEvent_t event = nullptr;
-        int64_t *h_off = nullptr;
-        CopyChunk *h_chunks = nullptr;
+        uint8_t *h_stage = nullptr;  // pinned: offsets, gather and scatter descriptors
         uint8_t *h_res = nullptr;
-        CopyChunk *d_chunks = nullptr;
+        uint8_t *d_stage = nullptr;  // device copy of h_stage
     };
     int fail(hipError_t e, const char *where) {
         char buf[256];

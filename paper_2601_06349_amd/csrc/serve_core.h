@@ -80,17 +80,17 @@ class Arena {
 };
 
 // Layout of one batch inside its arena region: packed input units, packed
-// output units, int64 offsets[B+1], uint8 results[B], each 256-byte aligned.
+// output units, uint8 results[B], each 256-byte aligned. (The batch's offsets
+// and copy descriptors travel in a small per-slot staging buffer.)
 struct BatchLayout {
-    int64_t in_off, out_off, offsets_off, results_off, bytes;
+    int64_t in_off, out_off, results_off, bytes;
 };
 
 inline BatchLayout layout(int64_t nreq, int64_t units) {
     BatchLayout l;
     l.in_off = 0;
     l.out_off = Arena::round_up(units * 2);
-    l.offsets_off = l.out_off + Arena::round_up(units * 2);
-    l.results_off = l.offsets_off + Arena::round_up(8 * (nreq + 1));
+    l.results_off = l.out_off + Arena::round_up(units * 2);
     l.bytes = l.results_off + Arena::round_up(nreq > 0 ? nreq : 1);
     return l;
 }

@@ -112,7 +112,7 @@ def test_oversize_rejected(env):
     cfg = S.make_config(num_streams=2, arena_bytes=1 << 20, max_batch_requests=64)
     out, st = S.run(_requests(env, with_dst=False), cfg)
     r = lambda b: (b + 255) // 256 * 256
-    big = np.array([2 * r(2 * int(L)) + r(16) + r(1) > (1 << 20) for L in env["lens"]])
+    big = np.array([2 * r(2 * int(L)) + r(1) > (1 << 20) for L in env["lens"]])
     assert np.all(out["status"][big] == wf.ERANGE)
     assert np.all(out["status"][~big] == 0)
     assert st["rejected"] == int(big.sum())

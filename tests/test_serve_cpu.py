@@ -12,7 +12,7 @@ from paper_2601_06349_amd import serve as S
 
 def _layout_bytes(nreq, units):
     r = lambda b: (b + 255) // 256 * 256
-    return 2 * r(2 * units) + r(8 * (nreq + 1)) + r(max(nreq, 1))
+    return 2 * r(2 * units) + r(max(nreq, 1))
 
 
 def test_budget_and_rejection():
@@ -84,7 +84,7 @@ def test_overlap_uses_all_slots():
 def test_memory_blocks_admission_until_free():
     """Two requests that each need most of the arena run one after the other
     even with free slots."""
-    arena = _layout_bytes(1, 30_000) + 1000
+    arena = _layout_bytes(1, 30_000) + 500
     arr = np.zeros(3, dtype=np.int64)
     lens = np.array([30_000, 30_000, 10])
     cfg = S.make_config(num_streams=4, arena_bytes=arena, max_batch_requests=1, max_batch_units=1 << 30)
