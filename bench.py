@@ -286,7 +286,34 @@ def host_resident(torch, wf, host_input):
         wf.utf16_to_well_formed_host(a, out=b)
         times.append(time.perf_counter() - t0)
     best = min(times)
+    # the link itself: plain copies of the same pinned buffers, one direction
+    # at a time and both at once on two streams
+    d = torch.empty(n, dtype=torch.int16, device="cuda")
+    d2 = torch.empty(n, dtype=torch.int16, device="cuda")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    h2d = timed(lambda: d.copy_(pin_in, non_blocking=True))
+    d2h = timed(lambda: pin_out.copy_(d, non_blocking=True))
+
+    def both():
+        with torch.cuda.stream(s1):
+            d2.copy_(pin_in, non_blocking=True)
+        with torch.cuda.stream(s2):
+            pin_out.copy_(d, non_blocking=True)
+
+    duplex = timed(both)
+    del d, d2
     return {"units": n, "best_s": round(best, 4), "input_GBps": round(2 * n / best / 1e9, 2),
+            "link_h2d_GBps": round(2 * n / h2d / 1e9, 2), "link_d2h_GBps": round(2 * n / d2h / 1e9, 2),
+            "link_both_directions_GBps_each": round(2 * n / duplex / 1e9, 2),
             "note": "pinned host in and out, 16 Mi-unit chunks on 3 streams; includes both PCIe transfers"}
 
 
@@ -303,7 +330,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
         sys.exit(2)
 

@@ -27,7 +27,7 @@ def _declared_functions():
 def L():
     from paper_2601_06349_amd import _lib
     if not os.path.exists(_lib.LIB_PATH):
-        pytest.fail("libutf16wf.so is not built (run __graft_entry__.build())")
+        pytest.fail("libutf16wf.so is not built (run python -m paper_2601_06349_amd.build)")
     return _lib.lib()
 
 
