@@ -126,3 +126,45 @@ def test_serve_workload_short(env):
     log(f"serve workload: {summ}")
     assert summ["completed"] == summ["requests"]
     assert summ["p99_ms"] >= summ["p50_ms"] > 0
+
+
+@pytest.mark.slow
+def test_serve_full_config_sampled():
+    """The full serving configuration: Poisson arrivals at 50,000 requests/s
+    for 60 s (about 3M requests), Zipf(1.1) lengths up to 2^24 units,
+    per-request lone-surrogate rate 10^U(-6,-1) via 16 device pools, a 64 GB
+    arena. Every 1000th request is delivered to its own destination and
+    checked against the oracle on its payload; every request must complete."""
+    torch = torch_mod()
+    from paper_2601_06349_amd import serve as S
+    from paper_2601_06349_amd import tune
+    tune.apply_cache()
+    pool_len = 1 << 24
+    sch = W.serve_schedule(60.0, rate_hz=50_000, n_pools=16, pool_len=pool_len, max_len=pool_len)
+    n = sch["length"].size
+    log(f"serve full: {n} requests")
+    pools = W.serve_pools(sch["pool_rates"], pool_len=pool_len)
+    d_pools = [torch.from_numpy(p.view(np.int16)).cuda() for p in pools]
+    base = np.array([p.data_ptr() for p in d_pools], dtype=np.uint64)
+    reqs = np.zeros(n, dtype=S.REQUEST_DTYPE)
+    reqs["arrival_ns"] = sch["arrival_ns"]
+    reqs["src"] = base[sch["pool"]] + 2 * sch["pool_offset"].astype(np.uint64)
+    reqs["length"] = sch["length"]
+    sample = np.arange(0, n, 1000)
+    dst_off = np.concatenate([[0], np.cumsum(sch["length"][sample])])
+    d_dst = torch.empty(int(dst_off[-1]) + 8, dtype=torch.int16, device="cuda")
+    reqs["dst"][sample] = np.uint64(d_dst.data_ptr()) + 2 * dst_off[:-1].astype(np.uint64)
+    torch.cuda.synchronize()
+    out, st = S.run(reqs, S.make_config(num_streams=4, arena_bytes=64 << 30))
+    summ = S.latency_summary(out, sch["arrival_ns"], sch["length"])
+    log(f"serve full: {summ} {st}")
+    assert np.all(out["status"] == 0) and st["completed"] == n
+    host = d_dst.cpu().numpy().view(np.uint16)
+    for j, i in enumerate(sample):
+        p, o, L = sch["pool"][i], sch["pool_offset"][i], sch["length"][i]
+        want = oracle.to_well_formed(pools[p][o:o + L])
+        assert np.array_equal(host[dst_off[j]:dst_off[j] + L], want), f"request {i}"
+    del d_pools, d_dst
+    torch.cuda.empty_cache()
+    import paper_2601_06349_amd as wf
+    wf.reset_params()
