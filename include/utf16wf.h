@@ -89,7 +89,7 @@ int utf16_locate_ill_formed(const uint16_t *in, int64_t n, int64_t *first_bad, i
  * repairs strings in the CPU's memory, Sec. 4): toWellFormed of h_in[0, n)
  * into h_out[0, n), both HOST memory (h_out == h_in repairs in place; any
  * other overlap is UTF16WF_EOVERLAP). The string moves through device
- * staging buffers in chunks of chunk_units (0 = 16 Mi units); each chunk is
+ * staging buffers in chunks of chunk_units (0 = 4 Mi units); each chunk is
  * copied in with one unit of context on each side, repaired, and its own
  * units copied back. Copies in, repairs and copies out of successive chunks
  * run on separate streams and overlap when the host buffers are pinned

@@ -568,12 +568,12 @@ int utf16_to_well_formed_host(const uint16_t *h_in, uint16_t *h_out, int64_t n, 
         return rc;
     if (overlap_not_equal(h_in, h_out, n))
         return fail(UTF16WF_EOVERLAP, "host input and output overlap without being equal");
-    const int64_t chunk = std::min<int64_t>(n, chunk_units > 0 ? chunk_units : (int64_t)1 << 24);
-    constexpr int kStages = 3;
+    const int64_t chunk = std::min<int64_t>(n, chunk_units > 0 ? chunk_units : (int64_t)1 << 22);
+    constexpr int kStages = 4;
     const int64_t nchunks = (n + chunk - 1) / chunk;
     const int stages = (int)std::min<int64_t>(kStages, nchunks);
     uint16_t *d_buf = nullptr;
-    hipStream_t st[kStages] = {nullptr, nullptr, nullptr};
+    hipStream_t st[kStages] = {nullptr, nullptr, nullptr, nullptr};
     // input and output staging of every stage start 128-byte aligned
     const int64_t stride = (chunk + 2 + 63) / 64 * 64;
     hipError_t e = hipMalloc((void **)&d_buf, (size_t)stages * 2 * (size_t)stride * sizeof(uint16_t));

@@ -57,6 +57,20 @@ struct CopyChunk {
 constexpr int64_t kCopyChunkUnits = 16384;
 hipError_t launch_chunk_copy(const CopyChunk *chunks, int64_t nchunks, hipStream_t stream);
 
+// A small batch's gather, passed by value as kernel arguments (no host to
+// device copy): the copy pieces, and the batch's offsets, which the kernel
+// also writes to `offsets_out` for the batch launch that follows.
+constexpr int kSmallBatchRequests = 32;
+constexpr int kSmallBatchChunks = 64;
+struct SmallGather {
+    CopyChunk chunks[kSmallBatchChunks];
+    int64_t offsets[kSmallBatchRequests + 1];
+    int64_t *offsets_out;
+    int32_t nchunks;
+    int32_t noffsets;
+};
+hipError_t launch_small_gather(const SmallGather &g, hipStream_t stream);
+
 // Batch isWellFormed of few long strings: clears the result of every
 // string of at least 8192 units with a mismatch among its first 512 units.
 hipError_t launch_head_check(const uint16_t *in_frame, const int64_t *offsets, int64_t nstr, int64_t shift,

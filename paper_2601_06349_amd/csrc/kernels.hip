@@ -289,8 +289,8 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
     // the search is long and its result gates the tile's offsets scan, so it
     // runs first and the scan's loads then overlap the data loads; with few
     // (long) strings it is short and runs after the first tile's loads are
-    // in flight. OP_IS always searches first (its skip test needs it before
-    // any load). Measured on the 1M-string and 4096-string batches.
+    // in flight (isWellFormed of few strings needs it before any load, for
+    // its skip test). Measured on the 1M-string and 4096-string batches.
     int64_t cursor = -1;
     if constexpr (BATCH) {
         if (a.nstr > 65536)
@@ -336,9 +336,13 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
         u32x4 v[R];
         TileStarts ts{0, 0, false, false, false};
 
-        if constexpr (BATCH && OP == kOpIs) {
-            // Check first whether the whole tile lies in a string already
-            // known to be ill-formed; then its data need not be read at all.
+        // Batch isWellFormed of few (long) strings checks first whether the
+        // whole tile lies in a string already known to be ill-formed; then
+        // its data need not be read at all. With many short strings a tile
+        // holds dozens of them, the check never fires, and the tile's loads
+        // go first as for the other operations.
+        const bool skip_first = BATCH && OP == kOpIs && a.nstr <= 65536;
+        if (skip_first) {
             if (cursor < 0)
                 cursor = lower_bound_wave(off, a.nstr + 1, tl - shift, lane);
             ts = scan_starts<R>(off, a.nstr, shift, cursor, tl, th, bm, lane, bm_dirty);
@@ -365,7 +369,7 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
         }
         if constexpr (OP == kOpIs && !BATCH)
             poll = __hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if constexpr (BATCH && OP != kOpIs) {
+        if (BATCH && !skip_first) {
             if (cursor < 0)
                 cursor = lower_bound_wave(off, a.nstr + 1, tl - shift, lane);
             ts = scan_starts<R>(off, a.nstr, shift, cursor, tl, th, bm, lane, bm_dirty);
@@ -662,6 +666,17 @@ __device__ __forceinline__ u32x4 realign(u32x4 a, u32x4 b, uint32_t sh) {
     return o;
 }
 
+__device__ void copy_chunk(const CopyChunk &c);
+
+// Small-batch gather: workgroup b copies piece b; workgroup 0 also writes the
+// offsets.
+__global__ void __launch_bounds__(256) small_gather_kernel(SmallGather g) {
+    if (blockIdx.x == 0 && (int)threadIdx.x < g.noffsets)
+        g.offsets_out[threadIdx.x] = g.offsets[threadIdx.x];
+    if ((int)blockIdx.x < g.nchunks)
+        copy_chunk(g.chunks[blockIdx.x]);
+}
+
 // Copies each chunk (one workgroup per chunk) with 16-byte stores: after a
 // head that aligns the destination, each 16-byte destination vector is built
 // from the two aligned 16-byte source vectors it straddles (when source and
@@ -669,7 +684,10 @@ __device__ __forceinline__ u32x4 realign(u32x4 a, u32x4 b, uint32_t sh) {
 // the last vector and the tail go unit by unit, so no source byte past the
 // chunk is ever read.
 __global__ void __launch_bounds__(256) chunk_copy_kernel(const CopyChunk *chunks) {
-    const CopyChunk c = chunks[blockIdx.x];
+    copy_chunk(chunks[blockIdx.x]);
+}
+
+__device__ void copy_chunk(const CopyChunk &c) {
     const int64_t n = c.n;
     const uintptr_t sa = reinterpret_cast<uintptr_t>(c.src), da = reinterpret_cast<uintptr_t>(c.dst);
     const int64_t head = min(n, (int64_t)(((16u - (da & 15u)) & 15u) >> 1));
@@ -775,6 +793,12 @@ hipError_t launch_chunk_copy(const CopyChunk *chunks, int64_t nchunks, hipStream
     if (nchunks <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(chunk_copy_kernel, dim3((unsigned)nchunks), dim3(256), 0, s, chunks);
+    return hipGetLastError();
+}
+
+hipError_t launch_small_gather(const SmallGather &g, hipStream_t s) {
+    const unsigned blocks = (unsigned)max(1, g.nchunks);
+    hipLaunchKernelGGL(small_gather_kernel, dim3(blocks), dim3(256), 0, s, g);
     return hipGetLastError();
 }
 

@@ -145,14 +145,27 @@ class HipExec {
             h_off[i + 1] = pos;
         }
         const size_t stage_bytes = 8 * (size_t)(nb + 1) + sizeof(CopyChunk) * (size_t)(g + sc);
-        const int64_t *d_offs = reinterpret_cast<const int64_t *>(sl.d_stage);
+        int64_t *d_offs = reinterpret_cast<int64_t *>(sl.d_stage);
         const CopyChunk *d_gat = reinterpret_cast<const CopyChunk *>(sl.d_stage + 8 * (nb + 1));
         hipStream_t st = sl.stream;
         hipError_t e;
-        if ((e = hipMemcpyAsync(sl.d_stage, sl.h_stage, stage_bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
-            return fail(e, "copy offsets and descriptors");
-        if ((e = launch_chunk_copy(d_gat, g, st)) != hipSuccess)
-            return fail(e, "gather");
+        if (nb <= kSmallBatchRequests && g <= kSmallBatchChunks && sc == 0) {
+            // small batch: offsets and pieces ride in the gather kernel's
+            // arguments, which saves a copy launch and its dispatch gap
+            SmallGather sg;
+            memcpy(sg.chunks, gat, sizeof(CopyChunk) * (size_t)g);
+            memcpy(sg.offsets, h_off, 8 * (size_t)(nb + 1));
+            sg.offsets_out = d_offs;
+            sg.nchunks = (int32_t)g;
+            sg.noffsets = (int32_t)(nb + 1);
+            if ((e = launch_small_gather(sg, st)) != hipSuccess)
+                return fail(e, "small gather");
+        } else {
+            if ((e = hipMemcpyAsync(sl.d_stage, sl.h_stage, stage_bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
+                return fail(e, "copy offsets and descriptors");
+            if ((e = launch_chunk_copy(d_gat, g, st)) != hipSuccess)
+                return fail(e, "gather");
+        }
         int rc;
         if (cfg_.op == UTF16WF_OP_TO)
             rc = utf16wf_batch(UTF16WF_OP_TO, d_in, d_out, d_offs, nb, nullptr, nullptr, nullptr, pos, st);
