@@ -314,7 +314,7 @@ def host_resident(torch, wf, host_input):
     return {"units": n, "best_s": round(best, 4), "input_GBps": round(2 * n / best / 1e9, 2),
             "link_h2d_GBps": round(2 * n / h2d / 1e9, 2), "link_d2h_GBps": round(2 * n / d2h / 1e9, 2),
             "link_both_directions_GBps_each": round(2 * n / duplex / 1e9, 2),
-            "note": "pinned host in and out, 4 Mi-unit chunks on 4 streams; includes both PCIe transfers"}
+            "note": "pinned host in and out, 8 Mi-unit chunks, copies in on one stream, repair and copies out on another; includes both PCIe transfers"}
 
 
 def main():

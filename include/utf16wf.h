@@ -88,14 +88,16 @@ int utf16_locate_ill_formed(const uint16_t *in, int64_t n, int64_t *first_bad, i
 /* Host-resident input (not in the paper's interface; the paper's routine
  * repairs strings in the CPU's memory, Sec. 4): toWellFormed of h_in[0, n)
  * into h_out[0, n), both HOST memory (h_out == h_in repairs in place; any
- * other overlap is UTF16WF_EOVERLAP). The string moves through device
- * staging buffers in chunks of chunk_units (0 = 4 Mi units); each chunk is
+ * other overlap is UTF16WF_EOVERLAP). The string moves through three device
+ * staging slots in chunks of chunk_units (0 = 8 Mi units); each chunk is
  * copied in with one unit of context on each side, repaired, and its own
- * units copied back. Copies in, repairs and copies out of successive chunks
- * run on separate streams and overlap when the host buffers are pinned
- * (hipHostMalloc); pageable buffers work but are staged by the runtime.
- * Synchronous: returns when h_out is complete. Staging memory is allocated
- * per call and freed before returning. */
+ * units copied back. Copies in run on one stream, repairs and copies out on
+ * another, so both PCIe directions stay busy when the host buffers are
+ * pinned (hipHostMalloc); pageable buffers work but are staged by the
+ * runtime.
+ * Synchronous: returns when h_out is complete. The staging buffer (up to
+ * 256 MiB) and its streams are kept per device and reused by later calls;
+ * a call that finds them in use, or needs more, uses private ones. */
 int utf16_to_well_formed_host(const uint16_t *h_in, uint16_t *h_out, int64_t n, int64_t chunk_units);
 
 /* -------------------------------------------------------- ragged batch --- */

@@ -143,6 +143,48 @@ std::mutex g_ws_mu;
 Workspace g_ws[kMaxDevices];
 std::mutex g_validate_mu[kMaxDevices];
 
+// Host-resident repair: staging buffer, streams and events kept per device
+// between calls (at most kHostStagingCacheBytes; held until the process ends).
+constexpr int kHostStages = 3;
+constexpr size_t kHostStagingCacheBytes = (size_t)256 << 20;
+struct HostStaging {
+    std::mutex mu;
+    uint16_t *buf = nullptr;
+    size_t bytes = 0;
+    hipStream_t in = nullptr, out = nullptr;
+    hipEvent_t loaded[kHostStages] = {}, freed[kHostStages] = {};
+
+    int ensure_streams() {
+        hipError_t e;
+        if (!in && (e = hipStreamCreateWithFlags(&in, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "hipStreamCreateWithFlags");
+        if (!out && (e = hipStreamCreateWithFlags(&out, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "hipStreamCreateWithFlags");
+        for (int i = 0; i < kHostStages; ++i) {
+            if (!loaded[i] && (e = hipEventCreateWithFlags(&loaded[i], hipEventDisableTiming)) != hipSuccess)
+                return hip_fail(e, "hipEventCreateWithFlags");
+            if (!freed[i] && (e = hipEventCreateWithFlags(&freed[i], hipEventDisableTiming)) != hipSuccess)
+                return hip_fail(e, "hipEventCreateWithFlags");
+        }
+        return UTF16WF_OK;
+    }
+    void release() {
+        for (int i = 0; i < kHostStages; ++i) {
+            if (loaded[i])
+                (void)hipEventDestroy(loaded[i]);
+            if (freed[i])
+                (void)hipEventDestroy(freed[i]);
+        }
+        if (in)
+            (void)hipStreamDestroy(in);
+        if (out)
+            (void)hipStreamDestroy(out);
+        if (buf)
+            (void)hipFree(buf);
+    }
+};
+HostStaging g_host_staging[kMaxDevices];
+
 int workspace(int dev, Workspace **ws) {
     std::lock_guard<std::mutex> lk(g_ws_mu);
     if (!g_ws[dev].flag) {
@@ -568,48 +610,68 @@ int utf16_to_well_formed_host(const uint16_t *h_in, uint16_t *h_out, int64_t n, 
         return rc;
     if (overlap_not_equal(h_in, h_out, n))
         return fail(UTF16WF_EOVERLAP, "host input and output overlap without being equal");
-    const int64_t chunk = std::min<int64_t>(n, chunk_units > 0 ? chunk_units : (int64_t)1 << 22);
-    constexpr int kStages = 4;
+    const int64_t chunk = std::min<int64_t>(n, chunk_units > 0 ? chunk_units : (int64_t)1 << 23);
     const int64_t nchunks = (n + chunk - 1) / chunk;
-    const int stages = (int)std::min<int64_t>(kStages, nchunks);
-    uint16_t *d_buf = nullptr;
-    hipStream_t st[kStages] = {nullptr, nullptr, nullptr, nullptr};
+    const int stages = (int)std::min<int64_t>(kHostStages, nchunks);
     // input and output staging of every stage start 128-byte aligned
     const int64_t stride = (chunk + 2 + 63) / 64 * 64;
-    hipError_t e = hipMalloc((void **)&d_buf, (size_t)stages * 2 * (size_t)stride * sizeof(uint16_t));
-    if (e != hipSuccess)
-        return hip_fail(e, "hipMalloc(staging)");
-    rc = UTF16WF_OK;
-    for (int i = 0; i < stages && rc == UTF16WF_OK; ++i)
-        if ((e = hipStreamCreateWithFlags(&st[i], hipStreamNonBlocking)) != hipSuccess)
-            rc = hip_fail(e, "hipStreamCreateWithFlags");
+    const size_t need = (size_t)stages * 2 * (size_t)stride * sizeof(uint16_t);
+    int dev;
+    if ((rc = current_device(&dev)) != UTF16WF_OK)
+        return rc;
+    // Reuse the device's cached staging buffer, streams and events when they
+    // are free and the staging is modest; otherwise (a concurrent call, or
+    // very large chunks) use private ones for this call.
+    HostStaging &cache = g_host_staging[dev];
+    std::unique_lock<std::mutex> lk(cache.mu, std::try_to_lock);
+    const bool cached = lk.owns_lock() && need <= kHostStagingCacheBytes;
+    HostStaging priv;
+    HostStaging &hs = cached ? cache : priv;
+    hipError_t e;
+    if (hs.bytes < need) {
+        if (hs.buf)
+            (void)hipFree(hs.buf);
+        hs.buf = nullptr;
+        hs.bytes = 0;
+        if ((e = hipMalloc((void **)&hs.buf, need)) != hipSuccess)
+            return hip_fail(e, "hipMalloc(staging)");
+        hs.bytes = need;
+    }
+    rc = hs.ensure_streams();
+    // Two streams, one per copy direction: copies in run back to back on
+    // `in`, repairs and copies out on `out`; events hand each staging slot
+    // from one to the other, so both PCIe directions stay busy.
     for (int64_t c = 0; c < nchunks && rc == UTF16WF_OK; ++c) {
         const int s = (int)(c % stages);
-        uint16_t *d_in = d_buf + (size_t)s * 2 * stride;
+        uint16_t *d_in = hs.buf + (size_t)s * 2 * stride;
         uint16_t *d_out = d_in + stride;
         const int64_t a = c * chunk, b = std::min(n, a + chunk);
         const int64_t ca = a > 0 ? a - 1 : a, cb = b < n ? b + 1 : b;  // one unit of context each side
-        if ((e = hipMemcpyAsync(d_in, h_in + ca, (size_t)(cb - ca) * 2, hipMemcpyHostToDevice, st[s])) !=
-            hipSuccess) {
+        if (c >= stages && (e = hipStreamWaitEvent(hs.in, hs.freed[s], 0)) != hipSuccess) {
+            rc = hip_fail(e, "wait slot");
+            break;
+        }
+        if ((e = hipMemcpyAsync(d_in, h_in + ca, (size_t)(cb - ca) * 2, hipMemcpyHostToDevice, hs.in)) !=
+                hipSuccess ||
+            (e = hipEventRecord(hs.loaded[s], hs.in)) != hipSuccess ||
+            (e = hipStreamWaitEvent(hs.out, hs.loaded[s], 0)) != hipSuccess) {
             rc = hip_fail(e, "copy in");
             break;
         }
-        if ((rc = utf16_to_well_formed(d_in, d_out, cb - ca, st[s])) != UTF16WF_OK)
+        if ((rc = utf16_to_well_formed(d_in, d_out, cb - ca, hs.out)) != UTF16WF_OK)
             break;
-        if ((e = hipMemcpyAsync(h_out + a, d_out + (a - ca), (size_t)(b - a) * 2, hipMemcpyDeviceToHost, st[s])) !=
-            hipSuccess) {
+        if ((e = hipMemcpyAsync(h_out + a, d_out + (a - ca), (size_t)(b - a) * 2, hipMemcpyDeviceToHost,
+                                hs.out)) != hipSuccess ||
+            (e = hipEventRecord(hs.freed[s], hs.out)) != hipSuccess) {
             rc = hip_fail(e, "copy out");
             break;
         }
     }
-    for (int i = 0; i < stages; ++i) {
-        if (st[i]) {
-            if ((e = hipStreamSynchronize(st[i])) != hipSuccess && rc == UTF16WF_OK)
-                rc = hip_fail(e, "synchronize");
-            (void)hipStreamDestroy(st[i]);
-        }
-    }
-    (void)hipFree(d_buf);
+    for (hipStream_t st : {hs.in, hs.out})
+        if (st && (e = hipStreamSynchronize(st)) != hipSuccess && rc == UTF16WF_OK)
+            rc = hip_fail(e, "synchronize");
+    if (!cached)
+        priv.release();
     return rc;
 }
 
