@@ -186,6 +186,9 @@ __device__ __forceinline__ int64_t string_of(const int64_t *off, int64_t shift, 
 struct TileStarts {
     int64_t kc;     // string holding unit tl (-1 if tl is before the first string)
     int64_t knext;  // first k with off[k] + shift >= th
+    int64_t k0;     // first k with off[k] + shift >= tl (the scan's cursor)
+    int32_t orel;   // window: min(off[k0 + lane] + shift - tl, tile units)
+    bool window;    // every start of the tile, and the first one past it, sit in orel
     bool next;      // a string starts at unit th
     bool inner;     // a string starts in (tl, th)
     bool any;       // a string starts in [tl, th) (the bitmap has a bit set)
@@ -211,10 +214,13 @@ __device__ __forceinline__ TileStarts scan_starts(const int64_t *off, int64_t ns
         dirty = false;
     }
     int64_t k = cursor, le = 0;
-    bool next = false, inner = false;
+    bool next = false, inner = false, first_round = true, window = false;
+    int32_t orel = 0;
     for (;;) {
         const int64_t idx = k + lane;
         const int64_t o = idx <= nstr ? off[idx] + shift : INT64_MAX;
+        if (first_round)
+            orel = o < tl ? 0 : (int32_t)min(o - tl, (int64_t)(kRowUnits * R));
         const bool lt = o < th;
         if (lt) {
             // with valid offsets tl <= o < th always holds here; the test
@@ -228,15 +234,100 @@ __device__ __forceinline__ TileStarts scan_starts(const int64_t *off, int64_t ns
         inner = inner || (__ballot(o > tl && lt) != 0);
         const int c = __popcll(__ballot(lt));
         k += c;
-        if (c < 64)
+        if (c < 64) {
+            window = first_round;
             break;
+        }
+        first_round = false;
     }
     const bool any = k != cursor;
     if (any) {
         wave_lds_sync();
         dirty = true;
     }
-    return TileStarts{cursor + le - 1, k, next, inner, any};
+    return TileStarts{cursor + le - 1, k, cursor, orel, window, next, inner, any};
+}
+
+// Number of lanes whose `orel` is <= p, for sorted `orel` with lane 63 above
+// every p asked (a tile's offsets window): a binary search over the lanes by
+// shuffles, six steps. All lanes of the wave must call it together.
+__device__ __forceinline__ int lanes_le(int32_t orel, int32_t p) {
+    int pos = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1) {
+        const int32_t v = __shfl(orel, pos + step - 1);
+        if (v <= p)
+            pos += step;
+    }
+    return pos;
+}
+
+// The flags of a lane's 8 units (bit 7 of each byte of A = units 0..3, B =
+// units 4..7) as 8 bits, bit j = unit j.
+__device__ __forceinline__ uint32_t pack8(uint32_t fA, uint32_t fB) {
+    const uint32_t a = (((fA >> 7) & 0x01010101u) * 0x01020408u) >> 24;
+    const uint32_t b = (((fB >> 7) & 0x01010101u) * 0x01020408u) >> 24;
+    return a | (b << 4);
+}
+
+// Batch check / locate of a tile that holds several strings: bit 8r + j of
+// `bits` marks a mismatch at unit tl + (64 r + lane) 8 + j. Each one is
+// charged to its string (the last k with off[k] + shift <= p): with the
+// tile's offsets in the lanes (ts.window), k = k0 - 1 + the number of them
+// at or below p, found by shuffles; otherwise by a search in memory. The
+// check clears results[k]; the locate adds the lane's mismatches of one
+// string up before its atomics. All lanes of the wave call it together.
+template <int OP>
+__device__ __forceinline__ void resolve_strings(const KernelArgs &a, const int64_t *off, int64_t shift,
+                                                const TileStarts &ts, int64_t tl, int lane, uint64_t bits) {
+    int64_t cur_k = -1;
+    uint64_t cur_first = 0, cur_count = 0;
+    auto flush = [&]() {
+        if (cur_k < 0)
+            return;
+        if constexpr (OP == kOpIs) {
+            __hip_atomic_store(a.results + cur_k, (uint8_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            atomicMin(reinterpret_cast<unsigned long long *>(a.first + cur_k), (unsigned long long)cur_first);
+            atomicAdd(reinterpret_cast<unsigned long long *>(a.count + cur_k), (unsigned long long)cur_count);
+        }
+    };
+    // p: the unit; k: its string; start: where that string begins
+    auto charge = [&](int64_t p, int64_t k, int64_t start) {
+        if (k != cur_k) {
+            flush();
+            cur_k = k;
+            cur_first = (uint64_t)(p - start);
+            cur_count = 0;
+        }
+        ++cur_count;
+    };
+    if (ts.window) {
+        while (__ballot(bits != 0ull)) {
+            const int b = bits ? __builtin_ctzll(bits) : 0;
+            const int pr = ((b >> 3) * 64 + lane) * 8 + (b & 7);
+            const int cnt = lanes_le(ts.orel, pr);
+            const int32_t sr = __shfl(ts.orel, cnt > 0 ? cnt - 1 : 0);
+            if (bits) {
+                bits &= bits - 1;
+                const int64_t k = min(max(ts.k0 + cnt - 1, (int64_t)0), a.nstr - 1);
+                // (a string's start is needed only when the lane reaches it
+                // first: its lane's offset, or, for the string that began
+                // before the tile, read from memory)
+                const int64_t start = (OP == kOpIs || k == cur_k) ? 0 : cnt > 0 ? tl + sr : off[k] + shift;
+                charge(tl + pr, k, start);
+            }
+        }
+    } else {
+        while (bits) {
+            const int b = __builtin_ctzll(bits);
+            bits &= bits - 1;
+            const int64_t p = tl + ((b >> 3) * 64 + lane) * 8 + (b & 7);
+            const int64_t k = string_of(off, shift, ts.kc, ts.knext, p, a.nstr);
+            charge(p, k, (OP == kOpIs || k == cur_k) ? 0 : off[k] + shift);
+        }
+    }
+    flush();
 }
 
 // ------------------------------------------------------------- the kernel
@@ -334,7 +425,7 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
         }
         const bool interior = tl >= lo && th <= hi;
         u32x4 v[R];
-        TileStarts ts{0, 0, false, false, false};
+        TileStarts ts{0, 0, 0, 0, false, false, false, false};
 
         // Batch isWellFormed of few (long) strings checks first whether the
         // whole tile lies in a string already known to be ill-formed; then
@@ -391,6 +482,7 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
         // flags live into phase 2 costs occupancy in the batch kernel but
         // measured faster than classifying again there.)
         uint32_t hA_[R], hB_[R], lA_[R], lB_[R], sbits[R];
+        uint64_t bad_bits = 0;  // batch check / locate: mismatches awaiting their string
         uint64_t hl[R], lf[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -476,19 +568,7 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
                         break;
                     }
                 } else {
-                    if (lane_bad) {
-                        uint64_t m = bad64;
-                        int64_t last_k = -1;
-                        while (m) {
-                            const int j = __builtin_ctzll(m) >> 3;
-                            m &= m - 1;
-                            const int64_t k = string_of(off, shift, ts.kc, ts.knext, u0 + j, a.nstr);
-                            if (k != last_k)
-                                __hip_atomic_store(a.results + k, (uint8_t)0, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-                            last_k = k;
-                        }
-                    }
+                    bad_bits |= (uint64_t)pack8(badA, badB) << (8 * r);
                 }
             } else {  // kOpLocate
                 if (!BATCH || single) {
@@ -503,20 +583,18 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
                         }
                     }
                 } else {
-                    if (lane_bad) {
-                        uint64_t m = bad64;
-                        while (m) {
-                            const int j = __builtin_ctzll(m) >> 3;
-                            m &= m - 1;
-                            const int64_t p = u0 + j;
-                            const int64_t k = string_of(off, shift, ts.kc, ts.knext, p, a.nstr);
-                            atomicMin(reinterpret_cast<unsigned long long *>(a.first + k),
-                                      (unsigned long long)(p - (off[k] + shift)));
-                            atomicAdd(reinterpret_cast<unsigned long long *>(a.count + k), 1ull);
-                        }
-                    }
+                    bad_bits |= (uint64_t)pack8(badA, badB) << (8 * r);
                 }
             }
+        }
+
+        // Batch check and locate, tiles holding several strings: find the
+        // string of each mismatched unit, after the rows (their registers
+        // are free by now). Bit 8r + j of bad_bits is unit j of the lane's
+        // group in row r, so a lane meets its units in increasing order.
+        if constexpr (BATCH && (OP == kOpIs || OP == kOpLocate)) {
+            if (!single && __ballot(bad_bits != 0ull))
+                resolve_strings<OP>(a, off, shift, ts, tl, lane, bad_bits);
         }
     }
 

@@ -122,6 +122,31 @@ def test_tiny_and_empty_strings(wf):
     wf.reset_params()
 
 
+def test_offsets_per_tile_around_one_wave(wf):
+    """Tiles holding 1, 2, 62, 63, 64, 65 and 200 offsets, with repeats
+    (empty strings) and dense surrogates: around 64 offsets per tile the
+    check and the locate switch between the tile's offsets kept in the wave's
+    lanes and a search in memory; both must name the same strings."""
+    rng = np.random.default_rng(11)
+    alphabet = np.array([A, H, L, 0xDBFF, 0xDC00, A], np.uint16)
+    for rows in ROWS:
+        _force_rows(wf, rows)
+        t = 512 * rows
+        starts = [0]
+        counts = [1, 2, 62, 63, 64, 65, 200] * 3
+        for i, c in enumerate(counts):
+            tl = (i + 1) * t  # tile 0 holds only the first string's start
+            pos = np.sort(rng.integers(tl, tl + t, size=c))
+            if i % 3 == 0:
+                pos[0] = tl  # a start exactly on the tile's first unit
+            starts.extend(pos.tolist())
+        total = (len(counts) + 1) * t + 37
+        off = np.array(starts + [total], np.int64)
+        buf = alphabet[rng.integers(0, alphabet.size, size=total)].astype(np.uint16)
+        _check_batch(wf, buf, off, what=f"offsets per tile rows={rows}")
+    wf.reset_params()
+
+
 def test_long_string_among_short(wf):
     rng = np.random.default_rng(5)
     lens = rng.integers(1, 50, size=2000)
