@@ -135,6 +135,25 @@ def cpu_baseline(inputs, budget_s=12.0):
     }
 
 
+def cpu_baseline_mt(inputs, passes=3):
+    """The chunked multi-threaded oracle over the same five buffers, on this
+    process's CPU share (at most 16 threads): best of a few passes."""
+    import oracle
+    lib = oracle._load()
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    out = np.empty(inputs[0].size, dtype=np.uint16)
+    units = sum(s.size for s in inputs)
+    best = float("inf")
+    for _ in range(passes):
+        t0 = time.perf_counter()
+        for s in inputs:
+            if lib.wf_to_chunked_mt(s.ctypes.data, out.ctypes.data, s.size, threads) < 0:
+                raise RuntimeError("oracle threads could not be created")
+        best = min(best, time.perf_counter() - t0)
+    return {"value": round(2.0 * units / best / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"the five buffers ({units} units), chunked multi-threaded oracle, best of {passes} passes"}
+
+
 def per_string_vs_batched(torch, wf, stream, sample=20000):
     """Ragged batch of 1,000,000 log-normal strings: one persistent launch
     against one flat launch per string (timed on a prefix sample)."""
@@ -434,6 +453,7 @@ def main():
     if not args.no_cpu and not args.profile:
         log("cpu baseline")
         result["cpu_baseline"] = cpu_baseline(host_inputs)
+        result["cpu_baseline_multithread"] = cpu_baseline_mt(host_inputs)
 
     if not args.no_extras and not args.profile:
         log("extras: in place, isWellFormed, copy ceiling")
