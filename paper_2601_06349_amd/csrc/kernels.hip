@@ -187,6 +187,7 @@ struct TileStarts {
     int64_t kc;     // string holding unit tl (-1 if tl is before the first string)
     int64_t knext;  // first k with off[k] + shift >= th
     int64_t k0;     // first k with off[k] + shift >= tl (the scan's cursor)
+    int64_t onext;  // off[knext] + shift (INT64_MAX past the last offset)
     int32_t orel;   // window: min(off[k0 + lane] + shift - tl, tile units)
     bool window;    // every start of the tile, and the first one past it, sit in orel
     bool next;      // a string starts at unit th
@@ -216,6 +217,7 @@ __device__ __forceinline__ TileStarts scan_starts(const int64_t *off, int64_t ns
     int64_t k = cursor, le = 0;
     bool next = false, inner = false, first_round = true, window = false;
     int32_t orel = 0;
+    int64_t onext = INT64_MAX;
     for (;;) {
         const int64_t idx = k + lane;
         const int64_t o = idx <= nstr ? off[idx] + shift : INT64_MAX;
@@ -236,6 +238,7 @@ __device__ __forceinline__ TileStarts scan_starts(const int64_t *off, int64_t ns
         k += c;
         if (c < 64) {
             window = first_round;
+            onext = (int64_t)__shfl((long long)o, c);  // the first offset at or past th
             break;
         }
         first_round = false;
@@ -245,7 +248,7 @@ __device__ __forceinline__ TileStarts scan_starts(const int64_t *off, int64_t ns
         wave_lds_sync();
         dirty = true;
     }
-    return TileStarts{cursor + le - 1, k, cursor, orel, window, next, inner, any};
+    return TileStarts{cursor + le - 1, k, cursor, onext, orel, window, next, inner, any};
 }
 
 // Number of lanes whose `orel` is <= p, for sorted `orel` with lane 63 above
@@ -412,6 +415,13 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
     // all its loads); later polls are issued with a tile's loads and read at
     // the next tile, so they add no latency.
     int32_t poll = 1;
+    // batch isWellFormed of few strings: the first offset past the previous
+    // tile (`nxt`, string `cursor` starts there) and the result byte of
+    // string cursor - 1, read with the previous tile's loads (`known`: the
+    // coming tile lies inside that string and pk holds its result)
+    int64_t nxt = -1;
+    uint8_t pk = 1;
+    bool pk_valid = false;
     if constexpr (OP == kOpIs && !BATCH) {
         if (__hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
             return;
@@ -425,7 +435,7 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
         }
         const bool interior = tl >= lo && th <= hi;
         u32x4 v[R];
-        TileStarts ts{0, 0, 0, 0, false, false, false, false};
+        TileStarts ts{0, 0, 0, 0, 0, false, false, false, false};
 
         // Batch isWellFormed of few (long) strings checks first whether the
         // whole tile lies in a string already known to be ill-formed; then
@@ -434,20 +444,37 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
         // go first as for the other operations.
         const bool skip_first = BATCH && OP == kOpIs && a.nstr <= 65536;
         if (skip_first) {
-            if (cursor < 0)
-                cursor = lower_bound_wave(off, a.nstr + 1, tl - shift, lane);
-            ts = scan_starts<R>(off, a.nstr, shift, cursor, tl, th, bm, lane, bm_dirty);
-            cursor = ts.knext;
-            if (!ts.inner && ts.kc >= 0 && ts.kc < a.nstr &&
-                __hip_atomic_load(a.results + ts.kc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-                // jump to the tile where string kc ends: the tiles before it
-                // lie inside kc and need neither a scan nor a load
-                const int64_t tn = (off[ts.kc + 1] + shift) / T;
-                if (tn > t + 1) {
-                    t = tn - 1;
-                    cursor = ts.kc + 1;  // off[kc] < tn * T <= off[kc + 1]
+            const bool known = pk_valid && nxt >= th;
+            pk_valid = false;
+            if (known) {
+                // No offset falls in [tl, th): the tile lies inside string
+                // cursor - 1, whose result came with the previous tile's
+                // loads, so neither a scan nor a wait precedes this tile's
+                // loads. Known ill-formed: jump to where the string ends.
+                if (pk == 0) {
+                    const int64_t tn = nxt / T;
+                    if (tn > t + 1)
+                        t = tn - 1;
+                    continue;
                 }
-                continue;
+                ts = TileStarts{cursor - 1, cursor, cursor, nxt, (int32_t)T, true, nxt == th, false, false};
+            } else {
+                if (cursor < 0)
+                    cursor = lower_bound_wave(off, a.nstr + 1, tl - shift, lane);
+                ts = scan_starts<R>(off, a.nstr, shift, cursor, tl, th, bm, lane, bm_dirty);
+                cursor = ts.knext;
+                nxt = ts.onext;
+                if (!ts.inner && ts.kc >= 0 && ts.kc < a.nstr &&
+                    __hip_atomic_load(a.results + ts.kc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                    // jump to the tile where string kc ends: the tiles before
+                    // it lie inside kc and need neither a scan nor a load
+                    const int64_t tn = (off[ts.kc + 1] + shift) / T;
+                    if (tn > t + 1) {
+                        t = tn - 1;
+                        cursor = ts.kc + 1;  // off[kc] < tn * T <= off[kc + 1]
+                    }
+                    continue;
+                }
             }
         }
 #pragma unroll
@@ -460,6 +487,12 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
         }
         if constexpr (OP == kOpIs && !BATCH)
             poll = __hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (skip_first && nxt >= th + T && cursor >= 1 && cursor - 1 < a.nstr) {
+            // the coming tile lies inside string cursor - 1: fetch its result
+            // now, with this tile's loads
+            pk = __hip_atomic_load(a.results + cursor - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            pk_valid = true;
+        }
         if (BATCH && !skip_first) {
             if (cursor < 0)
                 cursor = lower_bound_wave(off, a.nstr + 1, tl - shift, lane);
