@@ -5,14 +5,23 @@
  * those of Sec. 1 and Sec. 3.1 applied to each request alone.
  *
  * Requests arrive on a schedule (arrival times relative to the start of the
- * run). Each admitted request is copied from its device-resident payload into
- * a packed batch inside one device arena, repaired (or checked) there by one
- * batch launch, and, if the request names a destination, copied out. A
- * request is admitted when the arena has room for it (the HBM budget) and a
- * stream slot is free; batches on different slots run concurrently, and
- * requests that arrive while batches are on the GPU join the next batch as
- * soon as a slot and memory free up. Requests are admitted in arrival order
- * (no reordering).
+ * run). A request is admitted when the arena (one device allocation, the HBM
+ * budget) has room for its batch's region and a stream slot is free; batches
+ * on different slots run concurrently, and requests that arrive while
+ * batches are on the GPU join the next batch as soon as a slot and memory
+ * free up. Requests are admitted in arrival order (no reordering).
+ *
+ * A batch of at most 32 requests is one launch over the requests where they
+ * lie, each a string of its own: the repair goes straight from the payload
+ * to the destination (or into the batch's arena region when the request has
+ * none). A larger batch is packed: each payload is copied into the batch's
+ * arena region, one ragged-batch launch repairs (or checks) it there, and
+ * requests with a destination are copied out. Either way every request is
+ * repaired alone, as one string.
+ *
+ * Payloads and destinations of requests that may be in flight together must
+ * not overlap one another (a destination equal to its own payload is
+ * allowed: in place).
  *
  * Conventions as in utf16wf.h: device pointers, return UTF16WF_OK or a
  * negative status, utf16wf_last_error() for the message.
@@ -63,11 +72,16 @@ typedef struct {
     int64_t max_queue;         /* most requests waiting for admission */
     int64_t arena_peak_bytes;  /* most arena bytes in use at once */
     int64_t wall_ns;           /* from start to the last completion */
+    int64_t direct_batches;    /* batches launched as separate strings (no packing) */
 } utf16wf_serve_stats;
 
 /* Runs the loop on the current device until every request is completed,
  * rejected or timed out. Allocates the arena and per-slot buffers at the
- * start and frees them at the end. Outcomes has n entries. Synchronous. */
+ * start and frees them at the end. Outcomes has n entries. Synchronous.
+ * Before any HIP call, returns UTF16WF_EINVAL for a bad configuration, a
+ * negative length, a null payload or decreasing arrivals, UTF16WF_EALIGN
+ * for a pointer that is not 2-byte aligned, and UTF16WF_EOVERLAP for a
+ * destination that overlaps its own payload without being equal to it. */
 int utf16wf_serve_run(const utf16wf_serve_config *cfg, const utf16wf_serve_request *reqs, int64_t n,
                       utf16wf_serve_outcome *outcomes, utf16wf_serve_stats *stats);
 

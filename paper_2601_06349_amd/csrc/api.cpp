@@ -16,6 +16,7 @@
 #include <string>
 
 #include "../../include/utf16wf.h"
+#include "internal.h"
 #include "kernels.h"
 
 using namespace utf16wf;
@@ -344,11 +345,76 @@ int batch_call(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets
 }  // namespace
 
 namespace utf16wf {
-// Error reporting shared with the serving loop (serve.cpp).
+
 int set_error(int code, const char *msg) {
     g_err = msg;
     return code;
 }
+
+int strings_call(int op, int n, const uint16_t *const *src, uint16_t *const *dst, const int64_t *len,
+                 uint32_t *results, uint32_t stamp, hipStream_t stream) {
+    if (op != kOpTo && op != kOpIs)
+        return fail(UTF16WF_EINVAL, "strings: op must be the repair or the check");
+    if (n < 0 || n > kMultiMax)
+        return fail(UTF16WF_EINVAL, "strings: at most %d strings per launch", kMultiMax);
+    if (n > 0 && (!src || !len || (op == kOpTo && !dst)))
+        return fail(UTF16WF_EINVAL, "strings: null array");
+    if (op == kOpIs && n > 0 && (!results || (addr(results) & 3u)))
+        return fail(results ? UTF16WF_EALIGN : UTF16WF_EINVAL, "strings: results must be 4-byte aligned words");
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        if (len[i] < 0)
+            return fail(UTF16WF_EINVAL, "strings: length %d < 0", i);
+        if (len[i] == 0)
+            continue;
+        if (!src[i] || (op == kOpTo && !dst[i]))
+            return fail(UTF16WF_EINVAL, "strings: null pointer for string %d", i);
+        if ((addr(src[i]) & 1u) || (op == kOpTo && (addr(dst[i]) & 1u)))
+            return fail(UTF16WF_EALIGN, "strings: string %d is not 2-byte aligned", i);
+        if (op == kOpTo && overlap_not_equal(src[i], dst[i], len[i]))
+            return fail(UTF16WF_EOVERLAP, "strings: input and output of string %d overlap", i);
+        total += len[i];
+    }
+    if (total == 0)
+        return UTF16WF_OK;
+    int dev, cus, rc;
+    if ((rc = current_device(&dev)) != UTF16WF_OK || (rc = device_cus(dev, &cus)) != UTF16WF_OK)
+        return rc;
+    // each string is a frame of its own, tiled like a flat call of the
+    // batch's total size
+    const utf16wf_params p = get_params(op, 0, total);
+    const int64_t T = 512LL * p.rows;
+    MultiArgs a{};
+    int64_t tiles = 0;
+    for (int i = 0; i < n; ++i) {
+        MultiString &m = a.s[i];
+        m.tile0 = tiles;
+        if (len[i] == 0)
+            continue;
+        const int64_t ph = (int64_t)((addr(src[i]) & 15u) >> 1);
+        m.in = src[i] - ph;
+        m.out = op == kOpTo ? dst[i] - ph : nullptr;
+        m.lo = ph;
+        m.hi = ph + len[i];
+        m.scalar_store = (op == kOpTo && (addr(dst[i]) & 15u) != (addr(src[i]) & 15u)) ? 1 : 0;
+        tiles += (m.hi + T - 1) / T - m.lo / T;
+    }
+    a.ntiles = tiles;
+    a.n = n;
+    a.results = results;
+    a.stamp = stamp;
+    LaunchShape sh;
+    sh.rows = p.rows;
+    sh.wg_waves = p.wg_waves;
+    sh.nontemporal = p.nontemporal;
+    const int64_t waves = std::min<int64_t>(tiles, (int64_t)p.grid_per_cu * cus * p.wg_waves);
+    sh.grid = (int)std::max<int64_t>(1, (waves + p.wg_waves - 1) / p.wg_waves);
+    hipError_t e;
+    if ((e = launch_multi(op, sh, a, stream)) != hipSuccess)
+        return hip_fail(e, "strings: kernel launch");
+    return UTF16WF_OK;
+}
+
 }  // namespace utf16wf
 
 namespace {

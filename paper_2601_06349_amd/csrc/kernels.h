@@ -57,19 +57,36 @@ struct CopyChunk {
 constexpr int64_t kCopyChunkUnits = 16384;
 hipError_t launch_chunk_copy(const CopyChunk *chunks, int64_t nchunks, hipStream_t stream);
 
-// A small batch's gather, passed by value as kernel arguments (no host to
-// device copy): the copy pieces, and the batch's offsets, which the kernel
-// also writes to `offsets_out` for the batch launch that follows.
-constexpr int kSmallBatchRequests = 32;
-constexpr int kSmallBatchChunks = 64;
-struct SmallGather {
-    CopyChunk chunks[kSmallBatchChunks];
-    int64_t offsets[kSmallBatchRequests + 1];
-    int64_t *offsets_out;
-    int32_t nchunks;
-    int32_t noffsets;
+// Up to kMultiMax separate strings in one launch, each read from and written
+// to its own place (no packing into one buffer). Each string is tiled alone,
+// as the frame of a flat call: `in` / `out` are frame bases (unit u at in[u] /
+// out[u]; `in` 16-byte aligned), the string is units [lo, hi) of its frame.
+// Tiles are numbered string after string from 0 (`tile0` = the number of the
+// string's first tile, `ntiles` in all); the kernel's rows per tile fix the
+// tile size, so tile0 must be computed for the same rows.
+// Repair (kOpTo) writes every unit of every string; `scalar_store` marks a
+// string whose output phase (address mod 16) differs from its input's.
+// Check (kOpIs) writes `stamp` to results[i] when string i has a mismatch and
+// nothing otherwise: a string is well-formed iff its word differs from the
+// stamp afterwards, so the words need no clearing between launches as long
+// as every launch uses a new stamp.
+constexpr int kMultiMax = 32;
+struct MultiString {
+    const uint16_t *in;
+    uint16_t *out;
+    int64_t lo, hi;
+    int64_t tile0;
+    int32_t scalar_store;
+    int32_t pad_;
 };
-hipError_t launch_small_gather(const SmallGather &g, hipStream_t stream);
+struct MultiArgs {
+    MultiString s[kMultiMax];
+    int64_t ntiles;
+    uint32_t *results;
+    int32_t n;
+    uint32_t stamp;
+};
+hipError_t launch_multi(int op, const LaunchShape &shape, const MultiArgs &a, hipStream_t stream);
 
 // Batch isWellFormed of few long strings: clears the result of every
 // string of at least 8192 units with a mismatch among its first 512 units.

@@ -118,6 +118,23 @@ __device__ __forceinline__ uint32_t spread4(uint32_t b) {
     return ((b & 0xFu) * 0x00204081u & 0x01010101u) << 7;
 }
 
+// Mismatch flags of a lane's 8 units from their high / low flags (hA, lA:
+// units 0..3; hB, lB: units 4..7), the string-start flags sA, sB (a start
+// cuts the unit from its predecessor), whether the unit before the lane's
+// first is a high that may pair (hp) and whether the unit after its last is
+// a low that may pair (ln): a high whose successor is not a low, or a low
+// whose predecessor is not a high.
+__device__ __forceinline__ void mismatches(uint32_t hA, uint32_t hB, uint32_t lA, uint32_t lB, uint32_t sA,
+                                           uint32_t sB, uint32_t hp, uint32_t ln, uint32_t &badA, uint32_t &badB) {
+    const uint32_t lAp = lA & ~sA, lBp = lB & ~sB;
+    const uint32_t psA = ((hA << 8) | (hp << 7)) & ~sA;  // predecessor is high
+    const uint32_t psB = ((hB << 8) | (hA >> 24)) & ~sB;
+    const uint32_t nsA = (lAp >> 8) | (lBp << 24);        // successor is low
+    const uint32_t nsB = (lBp >> 8) | (ln << 31);
+    badA = (hA & ~nsA) | (lA & ~psA);
+    badB = (hB & ~nsB) | (lB & ~psB);
+}
+
 // Byte flags to 0xFF bytes.
 __device__ __forceinline__ uint32_t byte_mask(uint32_t f) { return f | (f - (f >> 7)); }
 
@@ -541,15 +558,8 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
             const uint32_t ln = (uint32_t)(nm >> lane) & 1u;
             // Phase 2: mismatches of the row's 8 units
             const uint32_t hA = hA_[r], hB = hB_[r], lA = lA_[r], lB = lB_[r];
-            const uint32_t sA = spread4(sbits[r]), sB = spread4(sbits[r] >> 4);
-            const uint32_t lAp = lA & ~sA, lBp = lB & ~sB;
-            // predecessor is high (cut at string starts) / successor is low
-            const uint32_t psA = ((hA << 8) | (hp << 7)) & ~sA;
-            const uint32_t psB = ((hB << 8) | (hA >> 24)) & ~sB;
-            const uint32_t nsA = (lAp >> 8) | (lBp << 24);
-            const uint32_t nsB = (lBp >> 8) | (ln << 31);
-            const uint32_t badA = (hA & ~nsA) | (lA & ~psA);
-            const uint32_t badB = (hB & ~nsB) | (lB & ~psB);
+            uint32_t badA, badB;
+            mismatches(hA, hB, lA, lB, spread4(sbits[r]), spread4(sbits[r] >> 4), hp, ln, badA, badB);
             const bool lane_bad = (badA | badB) != 0u;
             const uint64_t wave_bad = __ballot(lane_bad);
             const int64_t u0 = tl + ((int64_t)r * 64 + lane) * 8;
@@ -699,6 +709,93 @@ __global__ void __launch_bounds__(256) head_check_kernel(const uint16_t *in, con
         __hip_atomic_store(results + k, (uint8_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Separate strings in one launch (the MultiArgs layout): a wave takes a
+// contiguous run of the strings' tile numbers and handles each tile as a flat
+// call would, with its string's frame; tiles never span two strings.
+template <int OP, int R, bool NT>
+__global__ void __launch_bounds__(1024) wf_multi_kernel(MultiArgs a) {
+    constexpr int64_t T = kRowUnits * R;
+    const int lane = __lane_id();
+    const int64_t wg_waves = blockDim.x >> 6;
+    const int64_t nwaves = (int64_t)gridDim.x * wg_waves;
+    const int64_t wave = (int64_t)blockIdx.x * wg_waves + (threadIdx.x >> 6);
+    const int64_t per = (a.ntiles + nwaves - 1) / nwaves;
+    const int64_t vb = wave * per, ve = min(vb + per, a.ntiles);
+    if (vb >= ve)
+        return;
+    // the string of tile vb: the last one whose first tile is at or before
+    // it (of equal tile0, the last is the one that has tiles)
+    int i = __popcll(__ballot(lane < a.n && a.s[lane < a.n ? lane : 0].tile0 <= vb)) - 1;
+    // check: the result word of string poll_i as read with the previous
+    // tile's loads (once it holds the stamp, the string's other tiles are
+    // skipped)
+    int poll_i = -1;
+    uint32_t poll = 0;
+
+    for (int64_t vt = vb; vt < ve; ++vt) {
+        while (i + 1 < a.n && a.s[i + 1].tile0 <= vt)
+            ++i;
+        if constexpr (OP == kOpIs) {
+            if (poll_i == i && poll == a.stamp)
+                continue;
+        }
+        const uint16_t *in = a.s[i].in;
+        uint16_t *out = a.s[i].out;
+        const int64_t lo = a.s[i].lo, hi = a.s[i].hi;
+        const int64_t tl = (lo / T + (vt - a.s[i].tile0)) * T, th = tl + T;
+        const bool interior = tl >= lo && th <= hi;
+        u32x4 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t u0 = tl + ((int64_t)r * 64 + lane) * 8;
+            v[r] = interior ? ld16<NT>(in + u0) : ld_partial(in, u0, lo, hi);
+        }
+        if constexpr (OP == kOpIs) {
+            poll = __hip_atomic_load(a.results + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            poll_i = i;
+        }
+        uint32_t hA_[R], hB_[R], lA_[R], lB_[R];
+        uint64_t hl[R], lf[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            flags4(high_bytes(v[r].x, v[r].y), hA_[r], lA_[r]);
+            flags4(high_bytes(v[r].z, v[r].w), hB_[r], lB_[r]);
+            hl[r] = __ballot((hB_[r] >> 31) & 1u);
+            lf[r] = __ballot((lA_[r] >> 7) & 1u);
+        }
+        uint64_t carry_in = 0, carry_nx = 0;
+        if ((lf[0] & 1ull) && tl - 1 >= lo)
+            carry_in = is_high_unit(in[tl - 1]) ? 1ull : 0ull;
+        if ((hl[R - 1] >> 63) && th < hi)
+            carry_nx = is_low_unit(in[th]) ? 1ull : 0ull;
+        const bool ss = a.s[i].scalar_store != 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t pm = (hl[r] << 1) | (r == 0 ? carry_in : (hl[r - 1] >> 63));
+            const uint64_t nm = (lf[r] >> 1) | ((r == R - 1 ? carry_nx : (lf[r + 1] & 1ull)) << 63);
+            uint32_t badA, badB;
+            mismatches(hA_[r], hB_[r], lA_[r], lB_[r], 0u, 0u, (uint32_t)(pm >> lane) & 1u,
+                       (uint32_t)(nm >> lane) & 1u, badA, badB);
+            const uint64_t wave_bad = __ballot((badA | badB) != 0u);
+            if constexpr (OP == kOpTo) {
+                const int64_t u0 = tl + ((int64_t)r * 64 + lane) * 8;
+                const u32x4 o = wave_bad ? repair(v[r], badA, badB) : v[r];
+                if (interior && !ss)
+                    st16<NT>(out + u0, o);
+                else
+                    st_partial(out, u0, lo, hi, o, 0x8080808080808080ull);
+            } else {
+                if (wave_bad) {
+                    if (lane == 0)
+                        __hip_atomic_store(a.results + i, a.stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    poll = a.stamp;
+                    break;
+                }
+            }
+        }
+    }
+}
+
 // Plain copy with the same tiling: the bandwidth ceiling for the repair.
 template <int R, bool NT>
 __global__ void __launch_bounds__(1024) copy_kernel(const uint16_t *in, uint16_t *out, int64_t lo, int64_t hi) {
@@ -778,15 +875,6 @@ __device__ __forceinline__ u32x4 realign(u32x4 a, u32x4 b, uint32_t sh) {
 }
 
 __device__ void copy_chunk(const CopyChunk &c);
-
-// Small-batch gather: workgroup b copies piece b; workgroup 0 also writes the
-// offsets.
-__global__ void __launch_bounds__(256) small_gather_kernel(SmallGather g) {
-    if (blockIdx.x == 0 && (int)threadIdx.x < g.noffsets)
-        g.offsets_out[threadIdx.x] = g.offsets[threadIdx.x];
-    if ((int)blockIdx.x < g.nchunks)
-        copy_chunk(g.chunks[blockIdx.x]);
-}
 
 // Copies each chunk (one workgroup per chunk) with 16-byte stores: after a
 // head that aligns the destination, each 16-byte destination vector is built
@@ -879,6 +967,27 @@ hipError_t launch_copy_r(const uint16_t *in, uint16_t *out, int64_t lo, int64_t 
     return hipGetLastError();
 }
 
+template <int OP, int R>
+hipError_t launch_multi_r(const LaunchShape &sh, const MultiArgs &a, hipStream_t s) {
+    const dim3 grid((unsigned)sh.grid), block((unsigned)(64 * sh.wg_waves));
+    if (sh.nontemporal)
+        hipLaunchKernelGGL((wf_multi_kernel<OP, R, true>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((wf_multi_kernel<OP, R, false>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+template <int OP>
+hipError_t launch_multi_op(const LaunchShape &sh, const MultiArgs &a, hipStream_t s) {
+    switch (sh.rows) {
+    case 1: return launch_multi_r<OP, 1>(sh, a, s);
+    case 2: return launch_multi_r<OP, 2>(sh, a, s);
+    case 4: return launch_multi_r<OP, 4>(sh, a, s);
+    case 8: return launch_multi_r<OP, 8>(sh, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_main(int op, bool batch, const LaunchShape &shape, const KernelArgs &a, hipStream_t stream) {
@@ -907,10 +1016,16 @@ hipError_t launch_chunk_copy(const CopyChunk *chunks, int64_t nchunks, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_small_gather(const SmallGather &g, hipStream_t s) {
-    const unsigned blocks = (unsigned)max(1, g.nchunks);
-    hipLaunchKernelGGL(small_gather_kernel, dim3(blocks), dim3(256), 0, s, g);
-    return hipGetLastError();
+hipError_t launch_multi(int op, const LaunchShape &shape, const MultiArgs &a, hipStream_t s) {
+    if (a.ntiles <= 0 || a.n <= 0)
+        return hipSuccess;
+    if (a.n > kMultiMax)
+        return hipErrorInvalidValue;
+    switch (op) {
+    case kOpTo: return launch_multi_op<kOpTo>(shape, a, s);
+    case kOpIs: return launch_multi_op<kOpIs>(shape, a, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_head_check(const uint16_t *in_frame, const int64_t *offsets, int64_t nstr, int64_t shift,

@@ -2,15 +2,21 @@
 // serve_core.h driven by a HIP executor, and the same scheduler driven by a
 // simulated executor with a virtual clock.
 //
-// HIP executor, per batch on its slot's stream (default priority):
+// HIP executor, per batch on its slot's stream (default priority).
+// A batch of at most kMultiMax requests is one launch over the requests
+// where they lie (each request a string of its own, its descriptors in the
+// kernel's arguments): the repair goes straight to each destination, or to
+// the batch's arena region for requests without one; the check stamps a
+// per-slot result word. Larger batches are packed:
 //   1. the batch's offsets and its gather / scatter descriptors, packed
 //      together, in one copy from pinned host memory to the slot's device
 //      staging buffer;
 //   2. gather: each request's payload is copied into the packed input;
 //   3. one batch launch (utf16wf_batch) repairs into the packed output, or
 //      checks into per-string results;
-//   4. scatter to the requests' destinations (if any), result bytes D2H;
-//   5. an event; the loop polls it and then frees the region.
+//   4. scatter to the requests' destinations (if any).
+// Then result bytes (the check) come back to pinned host memory, and an
+// event follows; the loop polls it and then frees the region.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -23,15 +29,12 @@
 
 #include "../../include/utf16wf.h"
 #include "../../include/utf16wf_serve.h"
+#include "internal.h"
 #include "kernels.h"
 #include "serve_core.h"
 
 using namespace utf16wf;
 using namespace utf16wf::serve;
-
-namespace utf16wf {
-int set_error(int code, const char *msg);
-}
 
 namespace {
 
@@ -52,6 +55,8 @@ int check_config(const utf16wf_serve_config *c, int64_t n) {
 // ------------------------------------------------------------ HIP executor
 
 class HipExec {
+    struct Slot;
+
   public:
     HipExec(const utf16wf_serve_config &cfg, const utf16wf_serve_request *reqs, int64_t n)
         : cfg_(cfg), reqs_(reqs), n_(n) {}
@@ -81,6 +86,13 @@ class HipExec {
                 return fail(e, "hipHostMalloc");
             if ((e = hipMalloc((void **)&sl.d_stage, stage)) != hipSuccess)
                 return fail(e, "hipMalloc(staging)");
+            // result words of batches launched as separate strings: zero,
+            // and stamps start at 1
+            if ((e = hipMalloc((void **)&sl.d_words, 4 * kMultiMax)) != hipSuccess ||
+                (e = hipHostMalloc((void **)&sl.h_words, 4 * kMultiMax, 0)) != hipSuccess)
+                return fail(e, "result words");
+            if ((e = hipMemset(sl.d_words, 0, 4 * kMultiMax)) != hipSuccess)
+                return fail(e, "hipMemset(result words)");
         }
         t0_ = std::chrono::steady_clock::now();
         return UTF16WF_OK;
@@ -102,6 +114,10 @@ class HipExec {
                 (void)hipHostFree(sl.h_res);
             if (sl.d_stage)
                 (void)hipFree(sl.d_stage);
+            if (sl.d_words)
+                (void)hipFree(sl.d_words);
+            if (sl.h_words)
+                (void)hipHostFree(sl.h_words);
         }
         if (arena_)
             (void)hipFree(arena_);
@@ -118,6 +134,9 @@ class HipExec {
         uint16_t *d_out = reinterpret_cast<uint16_t *>(base + b.lay.out_off);
         uint8_t *d_res = base + b.lay.results_off;
         const int64_t nb = (int64_t)b.reqs.size();
+        sl.direct = nb <= kMultiMax;
+        if (sl.direct)
+            return launch_direct(b, sl, d_out);
         // count the copy pieces first, so offsets, gather and scatter
         // descriptors lie back to back in the staging buffer
         int64_t g = 0, sc = 0;
@@ -149,23 +168,10 @@ class HipExec {
         const CopyChunk *d_gat = reinterpret_cast<const CopyChunk *>(sl.d_stage + 8 * (nb + 1));
         hipStream_t st = sl.stream;
         hipError_t e;
-        if (nb <= kSmallBatchRequests && g <= kSmallBatchChunks && sc == 0) {
-            // small batch: offsets and pieces ride in the gather kernel's
-            // arguments, which saves a copy launch and its dispatch gap
-            SmallGather sg;
-            memcpy(sg.chunks, gat, sizeof(CopyChunk) * (size_t)g);
-            memcpy(sg.offsets, h_off, 8 * (size_t)(nb + 1));
-            sg.offsets_out = d_offs;
-            sg.nchunks = (int32_t)g;
-            sg.noffsets = (int32_t)(nb + 1);
-            if ((e = launch_small_gather(sg, st)) != hipSuccess)
-                return fail(e, "small gather");
-        } else {
-            if ((e = hipMemcpyAsync(sl.d_stage, sl.h_stage, stage_bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
-                return fail(e, "copy offsets and descriptors");
-            if ((e = launch_chunk_copy(d_gat, g, st)) != hipSuccess)
-                return fail(e, "gather");
-        }
+        if ((e = hipMemcpyAsync(sl.d_stage, sl.h_stage, stage_bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
+            return fail(e, "copy offsets and descriptors");
+        if ((e = launch_chunk_copy(d_gat, g, st)) != hipSuccess)
+            return fail(e, "gather");
         int rc;
         if (cfg_.op == UTF16WF_OP_TO)
             rc = utf16wf_batch(UTF16WF_OP_TO, d_in, d_out, d_offs, nb, nullptr, nullptr, nullptr, pos, st);
@@ -183,6 +189,49 @@ class HipExec {
         return UTF16WF_OK;
     }
 
+    // The batch as separate strings: one launch, no copies of the payloads.
+    int launch_direct(const Batch &b, Slot &sl, uint16_t *d_out) {
+        const int n = (int)b.reqs.size();
+        const uint16_t *src[kMultiMax];
+        uint16_t *dst[kMultiMax];
+        int64_t len[kMultiMax];
+        int64_t pos = 0;
+        for (int i = 0; i < n; ++i) {
+            const utf16wf_serve_request &r = reqs_[b.reqs[i]];
+            src[i] = r.src;
+            len[i] = r.length;
+            dst[i] = r.dst;
+            if (!r.dst) {
+                // into the arena region, at the input's phase (mod 8 units),
+                // so whole 16-byte vectors are stored; the layout reserves
+                // the 7 units this may skip per request
+                pos += (int64_t)(((reinterpret_cast<uintptr_t>(r.src) >> 1) - (uintptr_t)pos) & 7u);
+                dst[i] = d_out + pos;
+                pos += r.length;
+            }
+        }
+        hipStream_t st = sl.stream;
+        int rc;
+        hipError_t e;
+        if (cfg_.op == UTF16WF_OP_TO) {
+            rc = strings_call(kOpTo, n, src, dst, len, nullptr, 0u, st);
+        } else {
+            sl.stamp = (uint32_t)b.id + 1u;
+            rc = strings_call(kOpIs, n, src, nullptr, len, sl.d_words, sl.stamp, st);
+            if (rc == UTF16WF_OK &&
+                (e = hipMemcpyAsync(sl.h_words, sl.d_words, 4 * (size_t)n, hipMemcpyDeviceToHost, st)) != hipSuccess)
+                return fail(e, "copy result words");
+        }
+        if (rc != UTF16WF_OK)
+            return rc;
+        if ((e = hipEventRecord(sl.event, st)) != hipSuccess)
+            return fail(e, "hipEventRecord");
+        ++direct_batches_;
+        return UTF16WF_OK;
+    }
+
+    int64_t direct_batches() const { return direct_batches_; }
+
     int done(int slot) {
         const hipError_t e = hipEventQuery(slot_[slot].event);
         if (e == hipSuccess)
@@ -198,7 +247,7 @@ class HipExec {
             return;
         const Slot &sl = slot_[b.slot];
         for (size_t i = 0; i < b.reqs.size(); ++i)
-            out[b.reqs[i]].well_formed = sl.h_res[i];
+            out[b.reqs[i]].well_formed = sl.direct ? (sl.h_words[i] != sl.stamp ? 1 : 0) : sl.h_res[i];
     }
 
     void idle(int64_t next_arrival, bool any_busy) {
@@ -220,6 +269,10 @@ class HipExec {
         uint8_t *h_stage = nullptr;  // pinned: offsets, gather and scatter descriptors
         uint8_t *h_res = nullptr;
         uint8_t *d_stage = nullptr;  // device copy of h_stage
+        uint32_t *d_words = nullptr; // check results of a separate-strings batch
+        uint32_t *h_words = nullptr; // (pinned copy)
+        uint32_t stamp = 0;          // the stamp of the slot's last such batch
+        bool direct = false;         // the slot's batch runs as separate strings
     };
     int fail(hipError_t e, const char *where) {
         char buf[256];
@@ -230,7 +283,7 @@ class HipExec {
     utf16wf_serve_config cfg_;
     const utf16wf_serve_request *reqs_;
     int64_t n_;
-    int64_t max_chunks_ = 0, max_req_ = 0;
+    int64_t max_chunks_ = 0, max_req_ = 0, direct_batches_ = 0;
     void *arena_ = nullptr;
     std::vector<Slot> slot_;
     std::chrono::steady_clock::time_point t0_;
@@ -290,12 +343,19 @@ int utf16wf_serve_run(const utf16wf_serve_config *cfg, const utf16wf_serve_reque
             return set_error(UTF16WF_EALIGN, "request pointer not 2-byte aligned");
         if (i > 0 && reqs[i].arrival_ns < reqs[i - 1].arrival_ns)
             return set_error(UTF16WF_EINVAL, "arrivals must be non-decreasing");
+        const uintptr_t s = reinterpret_cast<uintptr_t>(reqs[i].src), d = reinterpret_cast<uintptr_t>(reqs[i].dst);
+        const uintptr_t bytes = 2u * (uintptr_t)reqs[i].length;
+        if (reqs[i].dst && s != d && s < d + bytes && d < s + bytes)
+            return set_error(UTF16WF_EOVERLAP, "request destination overlaps its payload without being equal");
         rq[(size_t)i] = Request{reqs[i].arrival_ns, reqs[i].length};
     }
     HipExec ex(*cfg, reqs, n);
     if ((rc = ex.init()) != UTF16WF_OK)
         return rc;
-    return run_loop(ex, *cfg, rq.data(), n, outcomes, stats);
+    rc = run_loop(ex, *cfg, rq.data(), n, outcomes, stats);
+    if (stats)
+        stats->direct_batches = ex.direct_batches();
+    return rc;
 }
 
 int utf16wf_serve_simulate(const utf16wf_serve_config *cfg, const int64_t *arrival_ns, const int64_t *lengths,

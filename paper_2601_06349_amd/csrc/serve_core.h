@@ -79,9 +79,11 @@ class Arena {
     int64_t total_ = 0, used_ = 0, peak_ = 0;
 };
 
-// Layout of one batch inside its arena region: packed input units, packed
-// output units, uint8 results[B], each 256-byte aligned. (The batch's offsets
-// and copy descriptors travel in a small per-slot staging buffer.)
+// Layout of one batch inside its arena region: packed input units, output
+// units, uint8 results[B], each 256-byte aligned. The output part has 16
+// bytes per request to spare, so that a request's output can start at its
+// input's address phase. (The batch's offsets and copy descriptors travel in
+// a small per-slot staging buffer.)
 struct BatchLayout {
     int64_t in_off, out_off, results_off, bytes;
 };
@@ -90,7 +92,7 @@ inline BatchLayout layout(int64_t nreq, int64_t units) {
     BatchLayout l;
     l.in_off = 0;
     l.out_off = Arena::round_up(units * 2);
-    l.results_off = l.out_off + Arena::round_up(units * 2);
+    l.results_off = l.out_off + Arena::round_up(units * 2 + 16 * nreq);
     l.bytes = l.results_off + Arena::round_up(nreq > 0 ? nreq : 1);
     return l;
 }

@@ -27,7 +27,8 @@ class ServeConfig(ctypes.Structure):
 
 class ServeStats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in ("batches", "completed", "rejected", "timed_out", "failed",
-                                               "max_inflight", "max_queue", "arena_peak_bytes", "wall_ns")]
+                                               "max_inflight", "max_queue", "arena_peak_bytes", "wall_ns",
+                                               "direct_batches")]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

@@ -80,6 +80,79 @@ def test_mix_equals_alone_and_oracle(env, streams, arena, max_req):
         assert st["batches"] < env["n"]
 
 
+def test_direct_and_packed_batches(env):
+    """Batches of at most 32 requests run as separate strings, larger ones
+    packed; both deliver the oracle's output, and both check correctly."""
+    S, wf = env["S"], env["wf"]
+    reqs = _requests(env)
+    # every batch at most 32 requests: all launched as separate strings
+    env["d_dst"].fill_(0x1234)
+    out, st = S.run(reqs, S.make_config(num_streams=4, arena_bytes=1 << 30, max_batch_requests=32))
+    assert np.all(out["status"] == 0) and st["direct_batches"] == st["batches"], st
+    _check_outputs(env, "separate strings")
+    # everything arrives at once on one stream: the first batches are large
+    # and packed, the tail may run as separate strings
+    burst = reqs.copy()
+    burst["arrival_ns"] = 0
+    env["d_dst"].fill_(0x1234)
+    out, st = S.run(burst, S.make_config(num_streams=1, arena_bytes=1 << 30, max_batch_requests=4096,
+                                         max_batch_units=1 << 22))
+    assert np.all(out["status"] == 0) and st["direct_batches"] < st["batches"], st
+    _check_outputs(env, "packed")
+    # the check, many separate-strings batches per slot (result words reused)
+    want = np.array([int(np.array_equal(w, env["pools"][env["pool"][i]][env["offs"][i]:env["offs"][i] +
+                                                                          env["lens"][i]]))
+                     for i, w in enumerate(env["want"])])
+    for max_req, arrival in ((8, reqs["arrival_ns"]), (4096, 0)):
+        r2 = _requests(env, with_dst=False)
+        r2["arrival_ns"] = arrival
+        out, st = S.run(r2, S.make_config(num_streams=2, op=wf.OP_IS, arena_bytes=1 << 30,
+                                          max_batch_requests=max_req, max_batch_units=1 << 22))
+        assert np.all(out["status"] == 0)
+        assert np.array_equal(out["well_formed"], want), f"check, max_req={max_req}: {st}"
+
+
+def test_in_place_and_no_destination(env):
+    """Requests repaired in place (destination = payload), and requests with
+    no destination (output kept in the arena) next to ones with one."""
+    torch, S = env["torch"], env["S"]
+    copies = [p.clone() for p in env["d_pools"]]
+    reqs = _requests(env)
+    base = np.array([p.data_ptr() for p in copies], dtype=np.uint64)
+    # non-overlapping slices of the copies, repaired in place
+    keep = np.zeros(env["n"], dtype=bool)
+    used = [[] for _ in copies]
+    for i in range(env["n"]):
+        p, o, L = env["pool"][i], env["offs"][i], env["lens"][i]
+        if L and all(o + L <= a or b <= o for a, b in used[p]):
+            used[p].append((o, o + L))
+            keep[i] = True
+    sub = reqs[keep].copy()
+    sub["src"] = base[env["pool"][keep]] + 2 * env["offs"][keep].astype(np.uint64)
+    sub["dst"] = sub["src"]
+    for max_req in (32, 4096):
+        for c, p in zip(copies, env["d_pools"]):
+            c.copy_(p)
+        out, st = S.run(sub, S.make_config(num_streams=2, arena_bytes=1 << 30, max_batch_requests=max_req))
+        assert np.all(out["status"] == 0)
+        host = [c.cpu().numpy().view(np.uint16) for c in copies]
+        idx = np.nonzero(keep)[0]
+        for i in idx:
+            p, o, L = env["pool"][i], env["offs"][i], env["lens"][i]
+            assert np.array_equal(host[p][o:o + L], env["want"][i]), f"in place {i} max_req={max_req}"
+    # every other request without a destination
+    mixed = _requests(env)
+    mixed["dst"][::2] = 0
+    env["d_dst"].fill_(0x1234)
+    out, st = S.run(mixed, S.make_config(num_streams=4, arena_bytes=1 << 30, max_batch_requests=32))
+    assert np.all(out["status"] == 0)
+    host = env["d_dst"].cpu().numpy().view(np.uint16)
+    for i in range(1, env["n"], 2):
+        got = host[env["dst_off"][i]:env["dst_off"][i] + env["lens"][i]]
+        assert np.array_equal(got, env["want"][i]), f"request {i}"
+    torch.cuda.synchronize()
+
+
 def test_alone_launches_equal_oracle(env):
     """The same requests, one flat launch each (alone), equal the oracle."""
     torch, wf = env["torch"], env["wf"]
@@ -112,7 +185,7 @@ def test_oversize_rejected(env):
     cfg = S.make_config(num_streams=2, arena_bytes=1 << 20, max_batch_requests=64)
     out, st = S.run(_requests(env, with_dst=False), cfg)
     r = lambda b: (b + 255) // 256 * 256
-    big = np.array([2 * r(2 * int(L)) + r(1) > (1 << 20) for L in env["lens"]])
+    big = np.array([r(2 * int(L)) + r(2 * int(L) + 16) + r(1) > (1 << 20) for L in env["lens"]])
     assert np.all(out["status"][big] == wf.ERANGE)
     assert np.all(out["status"][~big] == 0)
     assert st["rejected"] == int(big.sum())

@@ -12,7 +12,7 @@ from paper_2601_06349_amd import serve as S
 
 def _layout_bytes(nreq, units):
     r = lambda b: (b + 255) // 256 * 256
-    return 2 * r(2 * units) + r(max(nreq, 1))
+    return r(2 * units) + r(2 * units + 16 * nreq) + r(max(nreq, 1))
 
 
 def test_budget_and_rejection():
