@@ -153,6 +153,55 @@ def test_in_place_and_no_destination(env):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("rows", (1, 2, 4, 8))
+def test_separate_strings_tile_edges(env, rows):
+    """Batches run as separate strings, with the tile size forced: lengths
+    around one, two and three tiles and tiny ones, every input phase and
+    shifted output phases, dense lone surrogates; repair and check."""
+    torch, S, wf = env["torch"], env["S"], env["wf"]
+    T = 512 * rows
+    for op in (wf.OP_TO, wf.OP_IS):
+        wf.set_params(op, 0, -1, rows=rows, wg_waves=2, grid_per_cu=2, nontemporal=rows % 2)
+    try:
+        lens = [1, 2, 7, 8, 9, T - 1, T, T + 1, 2 * T - 1, 2 * T + 1, 3 * T + 5]
+        pools = (3, 4)  # 20 % lone surrogates; all surrogates
+        rng = np.random.default_rng(rows)
+        n = len(lens) * 8 * 2
+        reqs = np.zeros(n, dtype=S.REQUEST_DTYPE)
+        base = np.array([p.data_ptr() for p in env["d_pools"]], dtype=np.uint64)
+        want, slices, where, pos = [], [], [], 5
+        k = 0
+        for pool in pools:
+            for L in lens:
+                for phase in range(8):
+                    o = int(rng.integers(0, 1000)) * 8 + phase
+                    reqs["src"][k] = base[pool] + 2 * o
+                    reqs["length"][k] = L
+                    slices.append(env["pools"][pool][o:o + L])
+                    want.append(oracle.to_well_formed(slices[-1]))
+                    pos += int(rng.integers(0, 8))
+                    where.append(pos)
+                    pos += L
+                    k += 1
+        d_dst = torch.full((pos + 8,), 0x1234, dtype=torch.int16, device="cuda")
+        reqs["dst"] = np.uint64(d_dst.data_ptr()) + 2 * np.array(where, dtype=np.uint64)
+        out, st = S.run(reqs, S.make_config(num_streams=2, arena_bytes=1 << 28, max_batch_requests=32))
+        assert np.all(out["status"] == 0) and st["direct_batches"] == st["batches"]
+        host = d_dst.cpu().numpy().view(np.uint16)
+        for i in range(n):
+            got = host[where[i]:where[i] + reqs["length"][i]]
+            assert np.array_equal(got, want[i]), f"rows={rows} request {i} len {reqs['length'][i]}"
+        chk = reqs.copy()
+        chk["dst"] = 0
+        out, st = S.run(chk, S.make_config(num_streams=2, op=wf.OP_IS, arena_bytes=1 << 28,
+                                           max_batch_requests=32))
+        wf_want = np.array([int(oracle.is_well_formed(x)) for x in slices])
+        assert np.array_equal(out["well_formed"], wf_want), f"rows={rows} check"
+        del d_dst
+    finally:
+        wf.reset_params()
+
+
 def test_alone_launches_equal_oracle(env):
     """The same requests, one flat launch each (alone), equal the oracle."""
     torch, wf = env["torch"], env["wf"]
