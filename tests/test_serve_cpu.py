@@ -144,6 +144,35 @@ def test_argument_errors():
         S.simulate([0], [1], cfg)
 
 
+def test_run_rejects_bad_requests_before_any_device_call():
+    """utf16wf_serve_run checks every request before touching the device, so
+    these run without a GPU: fake, never dereferenced device addresses."""
+    A = 0x100000
+    cfg = S.make_config(num_streams=2, arena_bytes=1 << 20)
+
+    def reqs(*rows):
+        r = np.zeros(len(rows), dtype=S.REQUEST_DTYPE)
+        for i, (t, src, n, dst) in enumerate(rows):
+            r[i] = (t, src, n, dst)
+        return r
+
+    cases = [
+        (reqs((0, A, 10, A + 10)), wf.EOVERLAP),         # destination overlaps its payload
+        (reqs((0, A + 10, 10, A)), wf.EOVERLAP),
+        (reqs((0, A + 1, 10, 0)), wf.EALIGN),            # odd payload address
+        (reqs((0, A, 10, A + 4097)), wf.EALIGN),         # odd destination
+        (reqs((0, 0, 10, 0)), wf.EINVAL),                # null payload
+        (reqs((0, A, -1, 0)), wf.EINVAL),                # negative length
+        (reqs((5, A, 1, 0), (4, A, 1, 0)), wf.EINVAL),   # decreasing arrivals
+    ]
+    for r, code in cases:
+        with pytest.raises(wf.Utf16wfError) as e:
+            S.run(r, cfg)
+        assert e.value.code == code, (r, e.value)
+    with pytest.raises(wf.Utf16wfError):
+        S.run(reqs((0, A, 1, 0)), S.make_config(num_streams=17))
+
+
 def test_latency_summary():
     arr = np.arange(10, dtype=np.int64) * 1_000_000
     lens = np.full(10, 1000)
