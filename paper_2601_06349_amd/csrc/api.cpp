@@ -300,7 +300,11 @@ int batch_call(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets
     if ((rc = device_cus(dev, &cus)) != UTF16WF_OK)
         return rc;
     hipError_t e;
-    if (op == kOpIs) {
+    // few long strings (or an unknown total): check each string's head first
+    // so the main pass can skip strings whose first mismatch lies near their
+    // start; the head check also sets every result's initial value
+    const bool head = op == kOpIs && nstr <= 65536 && (units_hint == 0 || units_hint / nstr >= 8192);
+    if (op == kOpIs && !head) {
         if ((e = launch_fill_u8(results, 1, nstr, stream)) != hipSuccess)
             return hip_fail(e, "fill results");
     } else if (op == kOpLocate) {
@@ -328,10 +332,7 @@ int batch_call(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets
     a.first = first;
     a.count = count;
     a.scalar_store = (op == kOpTo && (addr(out) & 15u) != (addr(in) & 15u)) ? 1 : 0;
-    // few long strings (or an unknown total): check each string's head first
-    // so the main pass can skip strings whose first mismatch lies near their
-    // start
-    if (op == kOpIs && nstr <= 65536 && (units_hint == 0 || units_hint / nstr >= 8192)) {
+    if (head) {
         if ((e = launch_head_check(a.in, offsets, nstr, m, results, stream)) != hipSuccess)
             return hip_fail(e, "head check launch");
     }

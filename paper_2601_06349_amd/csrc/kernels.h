@@ -88,8 +88,9 @@ struct MultiArgs {
 };
 hipError_t launch_multi(int op, const LaunchShape &shape, const MultiArgs &a, hipStream_t stream);
 
-// Batch isWellFormed of few long strings: clears the result of every
-// string of at least 8192 units with a mismatch among its first 512 units.
+// Batch isWellFormed of few long strings, before the main pass: sets every
+// string's result, 0 for a string of at least 8192 units with a mismatch
+// among its first 512 units, else 1.
 hipError_t launch_head_check(const uint16_t *in_frame, const int64_t *offsets, int64_t nstr, int64_t shift,
                              uint8_t *results, hipStream_t stream);
 

@@ -671,13 +671,13 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
     }
 }
 
-// isWellFormed of a batch of few, long strings: one wave per string checks
-// the string's first 512 units (with the unit after them as context) and
-// clears the string's result when one of them is mismatched. Launched before
-// the main pass, it lets that pass skip every tile of a string whose first
-// mismatch lies near its start, which it cannot learn in time on its own: the
-// tiles of one string are all in flight together. Strings shorter than
-// kHeadMinUnits are left to the main pass.
+// isWellFormed of a batch of few, long strings, launched before the main
+// pass: one wave per string sets the string's result, to 0 when the string
+// has at least kHeadMinUnits units and a mismatch among its first 512 units
+// (with the unit after them as context), else to 1 (so no separate clearing
+// launch is needed). It lets the main pass skip every tile of a string whose
+// first mismatch lies near its start, which that pass cannot learn in time
+// on its own: the tiles of one string are all in flight together.
 constexpr int64_t kHeadMinUnits = 8192;
 __global__ void __launch_bounds__(256) head_check_kernel(const uint16_t *in, const int64_t *off, int64_t nstr,
                                                          int64_t shift, uint8_t *results) {
@@ -686,27 +686,24 @@ __global__ void __launch_bounds__(256) head_check_kernel(const uint16_t *in, con
     if (k >= nstr)
         return;
     const int64_t s0 = off[k] + shift, s1 = off[k + 1] + shift;
-    if (s1 - s0 < kHeadMinUnits)
-        return;
-    const int64_t hend = s0 + kRowUnits;  // s1 > hend: the head lies inside the string
-    const u32x4 v = ld_partial(in, s0 + (int64_t)lane * 8, s0, hend);
-    uint32_t hA, hB, lA, lB;
-    flags4(high_bytes(v.x, v.y), hA, lA);
-    flags4(high_bytes(v.z, v.w), hB, lB);
-    const uint64_t hl = __ballot((hB >> 31) & 1u);
-    const uint64_t lf = __ballot((lA >> 7) & 1u);
-    const uint64_t carry_nx = is_low_unit(in[hend]) ? 1ull : 0ull;  // context only
-    const uint32_t hp = (uint32_t)((hl << 1) >> lane) & 1u;  // nothing precedes the string
-    const uint32_t ln = (uint32_t)(((lf >> 1) | (carry_nx << 63)) >> lane) & 1u;
-    const uint32_t sA = lane == 0 ? 0x80u : 0u;  // unit s0 starts the string
-    const uint32_t lAp = lA & ~sA;
-    const uint32_t psA = ((hA << 8) | (hp << 7)) & ~sA;
-    const uint32_t psB = (hB << 8) | (hA >> 24);
-    const uint32_t nsA = (lAp >> 8) | (lB << 24);
-    const uint32_t nsB = (lB >> 8) | (ln << 31);
-    const uint32_t bad = ((hA & ~nsA) | (lA & ~psA)) | ((hB & ~nsB) | (lB & ~psB));
-    if (__ballot(bad != 0u) && lane == 0)
-        __hip_atomic_store(results + k, (uint8_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool clean = true;
+    if (s1 - s0 >= kHeadMinUnits) {
+        const int64_t hend = s0 + kRowUnits;  // s1 > hend: the head lies inside the string
+        const u32x4 v = ld_partial(in, s0 + (int64_t)lane * 8, s0, hend);
+        uint32_t hA, hB, lA, lB;
+        flags4(high_bytes(v.x, v.y), hA, lA);
+        flags4(high_bytes(v.z, v.w), hB, lB);
+        const uint64_t hl = __ballot((hB >> 31) & 1u);
+        const uint64_t lf = __ballot((lA >> 7) & 1u);
+        const uint64_t carry_nx = is_low_unit(in[hend]) ? 1ull : 0ull;  // context only
+        const uint32_t hp = (uint32_t)((hl << 1) >> lane) & 1u;           // nothing precedes the string
+        const uint32_t ln = (uint32_t)(((lf >> 1) | (carry_nx << 63)) >> lane) & 1u;
+        uint32_t badA, badB;
+        mismatches(hA, hB, lA, lB, lane == 0 ? 0x80u : 0u, 0u, hp, ln, badA, badB);  // unit s0 starts it
+        clean = __ballot((badA | badB) != 0u) == 0ull;
+    }
+    if (lane == 0)
+        results[k] = clean ? 1 : 0;
 }
 
 // Separate strings in one launch (the MultiArgs layout): a wave takes a
