@@ -47,10 +47,20 @@ def _check_batch(wf, buf, off, phase_in=0, phase_out=0, what="", hint=0):
     t_ip, _ = to_dev(buf, phase_in, pad=8)
     wf.utf16_to_well_formed_batch_inplace(t_ip, t_off)
     assert_same(to_host(t_ip), want_ip, f"batch inplace {what}")
-    res = wf.utf16_is_well_formed_batch(t_in, t_off).cpu().numpy()
+    if hint:
+        res_t = torch.empty(b, dtype=torch.uint8, device="cuda")
+        wf.utf16wf_batch(wf.OP_IS, t_in, t_off, results=res_t, units_hint=hint)
+        res = res_t.cpu().numpy()
+    else:
+        res = wf.utf16_is_well_formed_batch(t_in, t_off).cpu().numpy()
     want_res = oracle.is_well_formed_batch(buf, off)
     assert np.array_equal(res, want_res), f"batch is {what}: {np.nonzero(res != want_res)[0][:10]}"
-    first, cnt = wf.utf16_locate_ill_formed_batch(t_in, t_off)
+    if hint:
+        first = torch.empty(b, dtype=torch.int64, device="cuda")
+        cnt = torch.empty(b, dtype=torch.int64, device="cuda")
+        wf.utf16wf_batch(wf.OP_LOCATE, t_in, t_off, first=first, count=cnt, units_hint=hint)
+    else:
+        first, cnt = wf.utf16_locate_ill_formed_batch(t_in, t_off)
     wf_first, wf_cnt = oracle.locate_batch(buf, off)
     assert np.array_equal(first.cpu().numpy(), wf_first), f"batch first_bad {what}"
     assert np.array_equal(cnt.cpu().numpy(), wf_cnt), f"batch count {what}"
@@ -145,6 +155,24 @@ def test_offsets_per_tile_around_one_wave(wf):
         buf = alphabet[rng.integers(0, alphabet.size, size=total)].astype(np.uint16)
         _check_batch(wf, buf, off, what=f"offsets per tile rows={rows}")
     wf.reset_params()
+
+
+@pytest.mark.parametrize("nstr", (65536, 65537))
+def test_many_short_strings_at_the_search_switch(wf, nstr):
+    """65,536 strings (the check scans each tile's offsets before its loads
+    and skips strings already known bad) and 65,537 (it loads first), short
+    strings with empty ones, a few long ones, dense surrogates."""
+    rng = np.random.default_rng(nstr)
+    lens = rng.integers(0, 40, size=nstr)
+    lens[rng.integers(0, nstr, size=20)] = rng.integers(5000, 20000, size=20)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    buf = W.mix(int(off[-1]), 0.002, 77)
+    for k in rng.integers(0, nstr, size=500):  # lone surrogates at string edges
+        if lens[k]:
+            buf[off[k]] = L
+            buf[off[k + 1] - 1] = H
+    _check_batch(wf, buf, off, what=f"nstr={nstr}")
+    _check_batch(wf, buf, off, what=f"nstr={nstr} hinted", hint=int(off[-1]))
 
 
 def test_long_string_among_short(wf):
