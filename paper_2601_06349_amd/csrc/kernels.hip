@@ -30,7 +30,10 @@
 //     take contiguous runs of tiles and never communicate.
 //   * Ragged batches mark string starts in a per-wave LDS bitmap, filled from
 //     the offsets that fall inside the tile; a start cuts the pairing between
-//     a unit and its predecessor.
+//     a unit and its predecessor. The check and the locate find the string
+//     of a mismatch among the tile's offsets, which stay in the wave's lanes.
+//   * Up to 32 separate strings, each at its own address (a serving batch),
+//     run in one launch: each string is tiled alone, as a flat call's frame.
 #include "kernels.h"
 
 namespace utf16wf {
@@ -427,11 +430,6 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
         loc_first = ~0ull;
     };
 
-    // flat OP_IS early exit: the result word drops to 0 once any wave has
-    // seen a mismatch. The first poll waits (a wave that starts late skips
-    // all its loads); later polls are issued with a tile's loads and read at
-    // the next tile, so they add no latency.
-    int32_t poll = 1;
     // batch isWellFormed of few strings: the first offset past the previous
     // tile (`nxt`, string `cursor` starts there) and the result byte of
     // string cursor - 1, read with the previous tile's loads (`known`: the
@@ -439,6 +437,12 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
     int64_t nxt = -1;
     uint8_t pk = 1;
     bool pk_valid = false;
+
+    // flat OP_IS early exit: the result word drops to 0 once any wave has
+    // seen a mismatch. The first poll waits (a wave that starts late skips
+    // all its loads); later polls are issued with a tile's loads and read at
+    // the next tile, so they add no latency.
+    int32_t poll = 1;
     if constexpr (OP == kOpIs && !BATCH) {
         if (__hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
             return;
