@@ -147,8 +147,11 @@ int utf16wf_validate_offsets(const int64_t *offsets, int64_t num_strings, int64_
 /* A plan captures one batch call (its result initialisation and its
  * persistent kernel) into a HIP graph once; launching replays the graph on
  * `stream`. Buffers and num_strings are fixed at creation; their contents may
- * change between launches. The capture itself uses a private stream; `stream`
- * at creation is only used to pick the device. */
+ * change between launches. The capture itself uses a private stream. At
+ * creation the two ends of `offsets` are read on `stream` (which the call
+ * synchronises; it must not be capturing) and the units they span size the
+ * captured launch, as units_hint does for utf16wf_batch; offsets that change
+ * later stay correct, the launch shape may only fit them less well. */
 int utf16wf_batch_plan_create(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets,
                               int64_t num_strings, uint8_t *results, void *stream, void **plan);
 int utf16wf_batch_plan_launch(void *plan, void *stream);

@@ -546,7 +546,6 @@ int utf16wf_validate_offsets(const int64_t *offsets, int64_t num_strings, int64_
 
 int utf16wf_batch_plan_create(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets,
                               int64_t num_strings, uint8_t *results, void *stream, void **plan) {
-    (void)stream;
     if (!plan)
         return fail(UTF16WF_EINVAL, "null plan pointer");
     *plan = nullptr;
@@ -575,8 +574,23 @@ int utf16wf_batch_plan_create(int op, const uint16_t *in, uint16_t *out, const i
         return rc;
     }
     p->device = dev;
+    // the units the offsets span now pick the captured launch's shape (as a
+    // size hint does for a direct call); later contents stay correct
+    int64_t units = 0;
+    hipError_t e;
+    if (num_strings > 0) {
+        int64_t ends[2] = {0, 0};
+        hipStream_t st = (hipStream_t)stream;
+        if ((e = hipMemcpyAsync(&ends[0], offsets, 8, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(&ends[1], offsets + num_strings, 8, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess) {
+            delete p;
+            return hip_fail(e, "reading the offsets' ends");
+        }
+        units = std::max<int64_t>(0, ends[1] - ends[0]);
+    }
     hipStream_t cap;
-    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete p;
         return hip_fail(e, "hipStreamCreateWithFlags");
@@ -587,7 +601,7 @@ int utf16wf_batch_plan_create(int op, const uint16_t *in, uint16_t *out, const i
         delete p;
         return hip_fail(e, "hipStreamBeginCapture");
     }
-    rc = batch_call(op, in, out, offsets, num_strings, results, nullptr, nullptr, 0, cap);
+    rc = batch_call(op, in, out, offsets, num_strings, results, nullptr, nullptr, units, cap);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cap, &g);
     (void)hipStreamDestroy(cap);

@@ -221,8 +221,23 @@ def test_plans_replay(wf):
         torch.cuda.synchronize()
         assert_same(to_host(t_out), oracle.to_well_formed_batch(cur, off), f"plan replay {rep}")
         assert np.array_equal(res.cpu().numpy(), oracle.is_well_formed_batch(cur, off)), f"plan is {rep}"
+    # new boundaries (same number of strings, a different span): the shape
+    # picked at creation no longer fits, the results must still be exact
+    off2 = np.sort(rng.integers(0, buf.size + 1, size=off.size)).astype(np.int64)
+    off2[0] = 5
+    off2 = np.maximum(off2, 5)
+    t_off.copy_(torch.from_numpy(off2))
+    t_out.zero_()
+    res.fill_(7)
+    p_to.launch()
+    p_is.launch()
+    torch.cuda.synchronize()
+    want = oracle.to_well_formed_batch(cur, off2, out=np.zeros_like(cur))
+    assert_same(to_host(t_out), want, "plan replay, new offsets")
+    assert np.array_equal(res.cpu().numpy(), oracle.is_well_formed_batch(cur, off2)), "plan is, new offsets"
     p_to.close()
     p_is.close()
+    t_off.copy_(torch.from_numpy(off))
     # in-place plan
     t_ip, _ = to_dev(buf)
     p_ip = wf.BatchPlan(wf.OP_TO_INPLACE, t_ip, t_off)
