@@ -172,7 +172,10 @@ typedef struct {
 /* Set the parameters used for (op, batch 0/1, size class). size_class is
  * floor(log2(units)) in 0..40, or -1 for every class. */
 int utf16wf_set_params(int op, int batch, int size_class, const utf16wf_params *p);
-/* Parameters that a call of (op, batch, n units) would use. */
+/* Parameters that a call of (op, batch, n units) would use: those set for
+ * its size class; for a class with none set, those of the nearest class
+ * that has some (the smaller on a tie); the built-in defaults when no class
+ * of (op, batch) is set. */
 int utf16wf_get_params(int op, int batch, int64_t n, utf16wf_params *p);
 /* Back to the built-in defaults. */
 int utf16wf_reset_params(void);

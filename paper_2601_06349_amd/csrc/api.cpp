@@ -73,6 +73,7 @@ constexpr int kOps = 4;
 constexpr int kClasses = 41;
 std::mutex g_param_mu;
 utf16wf_params g_params[kOps][2][kClasses];
+bool g_params_set[kOps][2][kClasses];  // set by utf16wf_set_params (tuned)
 bool g_params_init = false;
 
 utf16wf_params default_params(int op, int batch, int cls) {
@@ -93,8 +94,10 @@ void init_params_locked() {
         return;
     for (int o = 0; o < kOps; ++o)
         for (int b = 0; b < 2; ++b)
-            for (int c = 0; c < kClasses; ++c)
+            for (int c = 0; c < kClasses; ++c) {
                 g_params[o][b][c] = default_params(o, b, c);
+                g_params_set[o][b][c] = false;
+            }
     g_params_init = true;
 }
 
@@ -111,10 +114,20 @@ bool params_ok(const utf16wf_params &p) {
            (p.nontemporal == 0 || p.nontemporal == 1);
 }
 
+// The parameters set for n's size class; for a class that has none, those
+// of the nearest class that has (the smaller on a tie), so sizes beyond the
+// tuned range keep a tuned shape; the built-in defaults if none is set.
 utf16wf_params get_params(int op, int batch, int64_t n) {
     std::lock_guard<std::mutex> lk(g_param_mu);
     init_params_locked();
-    return g_params[op][batch ? 1 : 0][size_class(n)];
+    const int b = batch ? 1 : 0, c = size_class(n);
+    for (int d = 0; d < kClasses; ++d) {
+        if (c - d >= 0 && g_params_set[op][b][c - d])
+            return g_params[op][b][c - d];
+        if (c + d < kClasses && g_params_set[op][b][c + d])
+            return g_params[op][b][c + d];
+    }
+    return g_params[op][b][c];
 }
 
 // Launch shape for a flat call over frame units [lo, hi), or for a batch with
@@ -655,10 +668,13 @@ int utf16wf_set_params(int op, int batch, int size_class_, const utf16wf_params 
     std::lock_guard<std::mutex> lk(g_param_mu);
     init_params_locked();
     if (size_class_ < 0) {
-        for (int c = 0; c < kClasses; ++c)
+        for (int c = 0; c < kClasses; ++c) {
             g_params[op][batch][c] = *p;
+            g_params_set[op][batch][c] = true;
+        }
     } else {
         g_params[op][batch][size_class_] = *p;
+        g_params_set[op][batch][size_class_] = true;
     }
     return UTF16WF_OK;
 }

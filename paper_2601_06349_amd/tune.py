@@ -186,12 +186,15 @@ def tune(quick=False, flat_classes=None, out=None, log=print):
             log(f"flat {names[op]:10s} 2^{c:2d}: tuned {ms * 1e3:9.1f} us  default {dms * 1e3:9.1f} us  {params}")
     del d_in, d_outs, d_tmp
 
-    # batches: the Zipf(1.1) 4096-string workload (launched without a size
-    # hint, so it sets the parameters for unknown sizes) and the 1,000,000
-    # log-normal strings (launched with their size hint)
+    # batches: the Zipf(1.1) 4096-string workload, launched without a size
+    # hint (it sets the parameters for unknown sizes) and with it (class 30,
+    # the nearest tuned class for large hinted batches), and the 1,000,000
+    # log-normal strings with their size hint (class 26, the nearest for
+    # smaller ones)
     zb, zoff, _ = W.zipf_batch()
     rb, roff = W.ragged_batch()
-    for label, buf, off, hinted in (("zipf_4096", zb, zoff, False), ("ragged_1m", rb, roff, True)):
+    for label, buf, off, hinted in (("zipf_4096", zb, zoff, False), ("zipf_4096", zb, zoff, True),
+                                    ("ragged_1m", rb, roff, True)):
         t_in = torch.from_numpy(buf.view(np.int16)).cuda()
         t_off = torch.from_numpy(off).cuda()
         t_out = torch.empty_like(t_in)
@@ -211,7 +214,7 @@ def tune(quick=False, flat_classes=None, out=None, log=print):
             entries.append({"op": op, "op_name": names[op], "batch": 1, "size_class": cls, "params": params,
                             "tuned_ms": round(ms, 5), "default_ms": round(dms, 5), "workload": label,
                             "units": nunits})
-            log(f"batch {label} {names[op]:10s}: tuned {ms:8.3f} ms  default {dms:8.3f} ms  {params}")
+            log(f"batch {label} class {cls} {names[op]:10s}: tuned {ms:8.3f} ms  default {dms:8.3f} ms  {params}")
         del t_in, t_off, t_out, t_ip
         torch.cuda.empty_cache()
 

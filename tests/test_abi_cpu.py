@@ -123,6 +123,8 @@ def test_params_roundtrip(L):
     assert wf.get_params(wf.OP_TO, 0, (1 << 28) + 5) == {"rows": 8, "wg_waves": 2, "grid_per_cu": 3,
                                                          "nontemporal": 1}
     assert wf.get_params(wf.OP_TO, 0, 1 << 27) == wf.get_params(wf.OP_TO, 0, (1 << 27) + 1)
+    # nearest set class: 2^30 units fall back to class 28
+    assert wf.get_params(wf.OP_TO, 0, 1 << 30)["rows"] == 8
     with pytest.raises(wf.Utf16wfError):
         wf.set_params(wf.OP_TO, 0, 28, rows=3, wg_waves=2, grid_per_cu=3, nontemporal=0)
     with pytest.raises(wf.Utf16wfError):
@@ -161,7 +163,15 @@ def test_tuning_cache_applies(tmp_path, L):
         assert wf.get_params(wf.OP_TO, 0, 1 << 20) == {"rows": 2, "wg_waves": 16, "grid_per_cu": 5,
                                                       "nontemporal": 1}
         assert wf.get_params(wf.OP_IS, 1, 1 << 40)["grid_per_cu"] == 64
-        assert wf.get_params(wf.OP_TO, 0, 1 << 21) != wf.get_params(wf.OP_TO, 0, 1 << 20)
+        # classes without an entry take the nearest class that has one
+        assert wf.get_params(wf.OP_TO, 0, 1 << 21) == wf.get_params(wf.OP_TO, 0, 1 << 20)
+        assert wf.get_params(wf.OP_TO, 0, 5) == wf.get_params(wf.OP_TO, 0, 1 << 20)
+        assert wf.get_params(wf.OP_IS, 1, 1 << 20)["grid_per_cu"] == 64
+        # an (op, batch) with no entry keeps the built-in defaults
+        wf.reset_params()
+        d = wf.get_params(wf.OP_LOCATE, 1, 1 << 30)
+        tune.apply_cache(str(path))
+        assert wf.get_params(wf.OP_LOCATE, 1, 1 << 30) == d
     finally:
         wf.reset_params()
 
