@@ -11,8 +11,8 @@
  * batches are on the GPU join the next batch as soon as a slot and memory
  * free up. Requests are admitted in arrival order (no reordering).
  *
- * A batch of at most 32 requests is one launch over the requests where they
- * lie, each a string of its own: the repair goes straight from the payload
+ * A batch of at most 32 requests (separate_max) is one launch over the
+ * requests where they lie, each a string of its own: the repair goes straight from the payload
  * to the destination (or into the batch's arena region when the request has
  * none). A larger batch is packed: each payload is copied into the batch's
  * arena region, one ragged-batch launch repairs (or checks) it there, and
@@ -43,6 +43,9 @@ typedef struct {
     int64_t max_batch_units;    /* a batch stops growing past this many units (>= 1) */
     int64_t timeout_ns;         /* a request still waiting this long after its
                                    arrival is dropped (0 = never) */
+    int64_t separate_max;       /* batches of at most this many requests run as
+                                   separate strings, larger ones packed: 0 = 32
+                                   (the most), 1..32, or -1 = always packed */
 } utf16wf_serve_config;
 
 typedef struct {

@@ -3,11 +3,11 @@
 // simulated executor with a virtual clock.
 //
 // HIP executor, per batch on its slot's stream (default priority).
-// A batch of at most kMultiMax requests is one launch over the requests
-// where they lie (each request a string of its own, its descriptors in the
-// kernel's arguments): the repair goes straight to each destination, or to
-// the batch's arena region for requests without one; the check stamps a
-// per-slot result word. Larger batches are packed:
+// A batch of at most separate_max requests (at most kMultiMax) is one launch
+// over the requests where they lie (each request a string of its own, its
+// descriptors in the kernel's arguments): the repair goes straight to each
+// destination, or to the batch's arena region for requests without one; the
+// check stamps a per-slot result word. Larger batches are packed:
 //   1. the batch's offsets and its gather / scatter descriptors, packed
 //      together, in one copy from pinned host memory to the slot's device
 //      staging buffer;
@@ -49,6 +49,8 @@ int check_config(const utf16wf_serve_config *c, int64_t n) {
         return set_error(UTF16WF_EINVAL, "op must be UTF16WF_OP_TO or UTF16WF_OP_IS");
     if (c->arena_bytes < 256 || c->max_batch_requests < 1 || c->max_batch_units < 1 || c->timeout_ns < 0)
         return set_error(UTF16WF_EINVAL, "bad arena / batch limits / timeout");
+    if (c->separate_max < -1 || c->separate_max > kMultiMax)
+        return set_error(UTF16WF_EINVAL, "separate_max must be -1..32");
     return UTF16WF_OK;
 }
 
@@ -59,7 +61,7 @@ class HipExec {
 
   public:
     HipExec(const utf16wf_serve_config &cfg, const utf16wf_serve_request *reqs, int64_t n)
-        : cfg_(cfg), reqs_(reqs), n_(n) {}
+        : cfg_(cfg), reqs_(reqs), n_(n), separate_max_(cfg.separate_max == 0 ? kMultiMax : cfg.separate_max) {}
 
     int init() {
         int64_t max_len = 0;
@@ -134,7 +136,7 @@ class HipExec {
         uint16_t *d_out = reinterpret_cast<uint16_t *>(base + b.lay.out_off);
         uint8_t *d_res = base + b.lay.results_off;
         const int64_t nb = (int64_t)b.reqs.size();
-        sl.direct = nb <= kMultiMax;
+        sl.direct = nb <= separate_max_;
         if (sl.direct)
             return launch_direct(b, sl, d_out);
         // count the copy pieces first, so offsets, gather and scatter
@@ -284,6 +286,7 @@ class HipExec {
     const utf16wf_serve_request *reqs_;
     int64_t n_;
     int64_t max_chunks_ = 0, max_req_ = 0, direct_batches_ = 0;
+    int64_t separate_max_;  // batches of at most this many requests: separate strings (-1: none)
     void *arena_ = nullptr;
     std::vector<Slot> slot_;
     std::chrono::steady_clock::time_point t0_;

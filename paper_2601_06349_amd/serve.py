@@ -22,7 +22,7 @@ OUTCOME_DTYPE = np.dtype([("launch_ns", "<i8"), ("done_ns", "<i8"), ("status", "
 class ServeConfig(ctypes.Structure):
     _fields_ = [("num_streams", ctypes.c_int32), ("op", ctypes.c_int32), ("arena_bytes", ctypes.c_int64),
                 ("max_batch_requests", ctypes.c_int64), ("max_batch_units", ctypes.c_int64),
-                ("timeout_ns", ctypes.c_int64)]
+                ("timeout_ns", ctypes.c_int64), ("separate_max", ctypes.c_int64)]
 
 
 class ServeStats(ctypes.Structure):
@@ -35,8 +35,11 @@ class ServeStats(ctypes.Structure):
 
 
 def make_config(num_streams=4, op=OP_TO, arena_bytes=64 << 30, max_batch_requests=4096,
-                max_batch_units=1 << 26, timeout_ns=0) -> ServeConfig:
-    return ServeConfig(num_streams, op, arena_bytes, max_batch_requests, max_batch_units, timeout_ns)
+                max_batch_units=1 << 26, timeout_ns=0, separate_max=0) -> ServeConfig:
+    """separate_max: batches of at most this many requests run as separate
+    strings (0 = the most, 32; -1 = every batch packed)."""
+    return ServeConfig(num_streams, op, arena_bytes, max_batch_requests, max_batch_units, timeout_ns,
+                       separate_max)
 
 
 def run(requests: np.ndarray, config: ServeConfig):
@@ -97,7 +100,7 @@ def latency_summary(outcomes, arrival_ns, lengths):
 
 def serve_workload(duration_s=5.0, rate_hz=50_000.0, num_streams=4, arena_bytes=64 << 30,
                    max_batch_requests=4096, max_batch_units=1 << 26, op=OP_TO, seed=None,
-                   pool_len=1 << 24, n_pools=16, log=None):
+                   pool_len=1 << 24, n_pools=16, separate_max=0, log=None):
     """The serving workload: Poisson arrivals at ``rate_hz`` for
     ``duration_s``, Zipf(1.1) lengths up to ``pool_len`` units, per-request
     lone-surrogate rate 10^U(-6,-1), payloads sliced from device-resident
@@ -119,11 +122,13 @@ def serve_workload(duration_s=5.0, rate_hz=50_000.0, num_streams=4, arena_bytes=
     reqs["length"] = sch["length"]
     torch.cuda.synchronize()
     cfg = make_config(num_streams=num_streams, op=op, arena_bytes=arena_bytes,
-                      max_batch_requests=max_batch_requests, max_batch_units=max_batch_units)
+                      max_batch_requests=max_batch_requests, max_batch_units=max_batch_units,
+                      separate_max=separate_max)
     out, st = run(reqs, cfg)
     summ = latency_summary(out, sch["arrival_ns"], sch["length"])
     summ.update({"requests": int(sch["length"].size), "duration_s": duration_s, "rate_hz": rate_hz,
-                 "num_streams": num_streams, "arena_bytes": arena_bytes, "stats": st})
+                 "num_streams": num_streams, "arena_bytes": arena_bytes, "separate_max": separate_max,
+                 "stats": st})
     del d_pools
     return summ
 

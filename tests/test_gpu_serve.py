@@ -99,6 +99,12 @@ def test_direct_and_packed_batches(env):
                                          max_batch_units=1 << 22))
     assert np.all(out["status"] == 0) and st["direct_batches"] < st["batches"], st
     _check_outputs(env, "packed")
+    # every batch packed (separate_max = -1), batches of one request included
+    env["d_dst"].fill_(0x1234)
+    out, st = S.run(reqs, S.make_config(num_streams=4, arena_bytes=1 << 30, max_batch_requests=32,
+                                        separate_max=-1))
+    assert np.all(out["status"] == 0) and st["direct_batches"] == 0, st
+    _check_outputs(env, "all packed")
     # the check, many separate-strings batches per slot (result words reused)
     want = np.array([int(np.array_equal(w, env["pools"][env["pool"][i]][env["offs"][i]:env["offs"][i] +
                                                                           env["lens"][i]]))

@@ -142,6 +142,9 @@ def test_argument_errors():
     cfg = S.make_config(num_streams=2, op=wf.OP_LOCATE)
     with pytest.raises(wf.Utf16wfError):
         S.simulate([0], [1], cfg)
+    for bad in (-2, 33):
+        with pytest.raises(wf.Utf16wfError):
+            S.simulate([0], [1], S.make_config(num_streams=2, separate_max=bad))
 
 
 def test_run_rejects_bad_requests_before_any_device_call():
