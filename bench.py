@@ -347,6 +347,35 @@ def host_resident(torch, wf, host_input):
             "note": "pinned host in and out, 8 Mi-unit chunks, copies in on one stream, repair and copies out on another; includes both PCIe transfers"}
 
 
+def profile_batches(torch, wf, W, reps=5):
+    """Short run for rocprofv3 over the batch workloads, in a fixed order:
+    for the 1,000,000-string batch (with its size hint) and then the
+    4096-string Zipf batch (without), `reps` calls each of the out-of-place
+    repair, the check and the locate; then one copy-kernel launch over
+    268,435,456 units (the counters' calibration)."""
+    for label, (buf, off), hinted in (("ragged 1M", W.ragged_batch(), True),
+                                      ("zipf 4096", W.zipf_batch()[:2], False)):
+        log(f"profile: {label}")
+        t_in = torch.from_numpy(buf.view(np.int16)).cuda()
+        t_off = torch.from_numpy(off).cuda()
+        t_out = torch.empty_like(t_in)
+        b = off.size - 1
+        res = torch.empty(b, dtype=torch.uint8, device="cuda")
+        first = torch.empty(b, dtype=torch.int64, device="cuda")
+        count = torch.empty(b, dtype=torch.int64, device="cuda")
+        hint = int(off[-1]) if hinted else 0
+        for op, kw in ((wf.OP_TO, {"out": t_out}), (wf.OP_IS, {"results": res}),
+                       (wf.OP_LOCATE, {"first": first, "count": count})):
+            for _ in range(reps):
+                wf.utf16wf_batch(op, t_in, t_off, units_hint=hint, **kw)
+            torch.cuda.synchronize()
+        del t_in, t_out
+        torch.cuda.empty_cache()
+    a = torch.zeros(N_UNITS, dtype=torch.int16, device="cuda")
+    wf.utf16wf_copy_units(a, torch.empty_like(a))
+    torch.cuda.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -357,6 +386,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="length of the serving run")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: the steps plus one copy-kernel launch, no extras")
+    ap.add_argument("--profile-batches", action="store_true",
+                    help="run for rocprofv3 over the batch workloads only (no JSON line)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -374,6 +405,9 @@ def main():
         sys.exit(2)
     wf.lib()  # fails loudly when the HIP library is missing
     tuned = tune.apply_cache()
+    if args.profile_batches:
+        profile_batches(torch, wf, W)
+        return
     stream = torch.cuda.current_stream()
 
     log("generating inputs")

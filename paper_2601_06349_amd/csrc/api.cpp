@@ -242,10 +242,8 @@ int flat_call(int op, const uint16_t *in, uint16_t *out, int64_t n, int32_t *fla
         if ((e = launch_fill_i32(flag, 1, 1, stream)) != hipSuccess)
             return hip_fail(e, "fill result");
     } else if (op == kOpLocate) {
-        if ((e = launch_fill_i64(first, -1, 1, stream)) != hipSuccess)
-            return hip_fail(e, "fill first_bad");
-        if ((e = launch_fill_i64(count, 0, 1, stream)) != hipSuccess)
-            return hip_fail(e, "fill count");
+        if ((e = launch_fill_locate(first, count, 1, stream)) != hipSuccess)
+            return hip_fail(e, "fill first_bad and count");
     }
     if (n == 0)
         return UTF16WF_OK;
@@ -321,10 +319,8 @@ int batch_call(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets
         if ((e = launch_fill_u8(results, 1, nstr, stream)) != hipSuccess)
             return hip_fail(e, "fill results");
     } else if (op == kOpLocate) {
-        if ((e = launch_fill_i64(first, -1, nstr, stream)) != hipSuccess)
-            return hip_fail(e, "fill first_bad");
-        if ((e = launch_fill_i64(count, 0, nstr, stream)) != hipSuccess)
-            return hip_fail(e, "fill count");
+        if ((e = launch_fill_locate(first, count, nstr, stream)) != hipSuccess)
+            return hip_fail(e, "fill first_bad and count");
     }
     const int64_t m = (int64_t)((addr(in) & 15u) >> 1);
     KernelArgs a{};

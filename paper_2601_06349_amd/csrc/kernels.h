@@ -45,7 +45,8 @@ hipError_t launch_main(int op, bool batch, const LaunchShape &shape, const Kerne
                        hipStream_t stream);
 hipError_t launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t stream);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t stream);
-hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t stream);
+// first[0, n) = -1 and count[0, n) = 0 in one launch (locate results).
+hipError_t launch_fill_locate(int64_t *first, int64_t *count, int64_t n, hipStream_t stream);
 hipError_t launch_copy(const uint16_t *in, uint16_t *out, int64_t lo, int64_t hi,
                        const LaunchShape &shape, hipStream_t stream);
 // One contiguous piece of a gather or scatter copy (at most kCopyChunkUnits).

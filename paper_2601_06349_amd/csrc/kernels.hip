@@ -831,11 +831,35 @@ __global__ void __launch_bounds__(1024) copy_kernel(const uint16_t *in, uint16_t
     }
 }
 
-template <typename T>
-__global__ void fill_kernel(T *p, T v, int64_t n) {
+// Fills up to two byte ranges (blockIdx.y picks one) with a repeating
+// 16-byte pattern: byte a of memory gets byte (a mod 16) of the pattern. A
+// range that starts on an element boundary of an element size dividing 16
+// thus holds the element value repeated. The 16-byte-aligned body is written
+// with vector stores, the unaligned head and tail byte by byte.
+struct FillRange {
+    uint8_t *p;
+    int64_t nbytes;
+    u32x4 pat;
+};
+__device__ __forceinline__ uint8_t pattern_byte(u32x4 pat, uint32_t k) {
+    const uint32_t d = k < 4 ? pat.x : k < 8 ? pat.y : k < 12 ? pat.z : pat.w;
+    return (uint8_t)(d >> (8 * (k & 3)));
+}
+__global__ void __launch_bounds__(256) fill_kernel(FillRange r0, FillRange r1) {
+    const FillRange &r = blockIdx.y == 0 ? r0 : r1;
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(r.p);
+    const int64_t head = min(r.nbytes, (int64_t)((16u - (a0 & 15u)) & 15u));
+    const int64_t nv = (r.nbytes - head) >> 4;
+    const int64_t tail = head + nv * 16;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        p[i] = v;
+    u32x4 *q = reinterpret_cast<u32x4 *>(r.p + head);
+    for (int64_t i = gid; i < nv; i += stride)
+        q[i] = r.pat;
+    if (gid < head)
+        r.p[gid] = pattern_byte(r.pat, (uint32_t)((a0 + gid) & 15u));
+    if (gid < r.nbytes - tail)
+        r.p[tail + gid] = pattern_byte(r.pat, (uint32_t)((a0 + tail + gid) & 15u));
 }
 
 __global__ void validate_kernel(const int64_t *off, int64_t nstr, int64_t buf_units, int32_t *bad) {
@@ -915,13 +939,34 @@ __device__ void copy_chunk(const CopyChunk &c) {
         c.dst[i] = c.src[i];
 }
 
+// The 16-byte pattern of element value v (size 1, 4 or 8 bytes).
+template <typename T>
+FillRange fill_range(T *p, T v, int64_t n) {
+    static_assert(16 % sizeof(T) == 0, "element size must divide 16");
+    FillRange r;
+    r.p = reinterpret_cast<uint8_t *>(p);
+    r.nbytes = n > 0 ? n * (int64_t)sizeof(T) : 0;
+    uint32_t w[4];
+    uint8_t *b = reinterpret_cast<uint8_t *>(w);
+    for (int i = 0; i < 16; ++i)
+        b[i] = reinterpret_cast<const uint8_t *>(&v)[i % sizeof(T)];
+    r.pat = (u32x4){w[0], w[1], w[2], w[3]};
+    return r;
+}
+
+hipError_t fill2(const FillRange &r0, const FillRange &r1, hipStream_t s) {
+    const int64_t nb = max(r0.nbytes, r1.nbytes);
+    if (nb <= 0)
+        return hipSuccess;
+    // one 16-byte store per thread, at most 2048 workgroups per range
+    const int64_t blocks = max((int64_t)1, min((nb / 16 + 255) / 256, (int64_t)2048));
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks, r1.nbytes > 0 ? 2u : 1u), dim3(256), 0, s, r0, r1);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t fill(T *p, T v, int64_t n, hipStream_t s) {
-    if (n <= 0)
-        return hipSuccess;
-    const int64_t blocks = min((n + 255) / 256, (int64_t)4096);
-    hipLaunchKernelGGL(fill_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
-    return hipGetLastError();
+    return fill2(fill_range(p, v, n), FillRange{nullptr, 0, (u32x4){0, 0, 0, 0}}, s);
 }
 
 template <int OP, bool BATCH, int R, bool NT>
@@ -997,7 +1042,9 @@ hipError_t launch_main(int op, bool batch, const LaunchShape &shape, const Kerne
 
 hipError_t launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s) { return fill<uint8_t>(p, v, n, s); }
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) { return fill<int32_t>(p, v, n, s); }
-hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s) { return fill<int64_t>(p, v, n, s); }
+hipError_t launch_fill_locate(int64_t *first, int64_t *count, int64_t n, hipStream_t s) {
+    return fill2(fill_range(first, (int64_t)-1, n), fill_range(count, (int64_t)0, n), s);
+}
 
 hipError_t launch_copy(const uint16_t *in, uint16_t *out, int64_t lo, int64_t hi, const LaunchShape &shape,
                        hipStream_t s) {

@@ -248,6 +248,25 @@ def test_plans_replay(wf):
     p_ip.close()
 
 
+def test_results_at_any_alignment(wf):
+    """Per-string results written into a byte buffer at odd offsets: the
+    initialisation fills exactly the strings' bytes, head and tail included."""
+    torch = torch_mod()
+    rng = np.random.default_rng(21)
+    for b in (1, 15, 16, 17, 3001):
+        buf, off = _random_batch(rng, b, 30, np.array([A, H, L], np.uint16))
+        t_in, _ = to_dev(buf)
+        t_off = offsets_dev(off)
+        want = oracle.is_well_formed_batch(buf, off)
+        for shift in (0, 1, 3, 7, 13):
+            for hint in (0, int(off[-1])):  # head pass sets the results / fill kernel does
+                big = torch.full((b + 40,), 0x5A, dtype=torch.uint8, device="cuda")
+                wf.utf16wf_batch(wf.OP_IS, t_in, t_off, results=big[shift:shift + b], units_hint=hint)
+                got = big.cpu().numpy()
+                assert np.array_equal(got[shift:shift + b], want), (b, shift, hint)
+                assert np.all(got[:shift] == 0x5A) and np.all(got[shift + b:] == 0x5A), (b, shift, hint)
+
+
 def test_validate_offsets(wf):
     good = offsets_dev(np.array([0, 3, 3, 10], np.int64))
     wf.utf16wf_validate_offsets(good, 10)
