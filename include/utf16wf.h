@@ -114,8 +114,10 @@ int utf16_to_well_formed_host(const uint16_t *h_in, uint16_t *h_out, int64_t n, 
 int utf16_is_well_formed_batch(const uint16_t *buf, const int64_t *offsets, int64_t num_strings,
                                uint8_t *results, void *stream);
 
-/* toWellFormed per string; out == in runs in place, other overlap is
- * UTF16WF_EOVERLAP. */
+/* toWellFormed per string into out, indexed by the same offsets (string k
+ * goes to out[offsets[k], offsets[k+1])). out == in runs in place; any other
+ * overlap of the two buffers is not allowed, and not checked (the span of
+ * the batch is only known on the device). */
 int utf16_to_well_formed_batch(const uint16_t *in, uint16_t *out, const int64_t *offsets,
                                int64_t num_strings, void *stream);
 
