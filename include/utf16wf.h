@@ -69,10 +69,11 @@ enum {
 int utf16_is_well_formed(const uint16_t *in, int64_t n, int32_t *result, void *stream);
 
 /* toWellFormed: out[0, n) = in[0, n) with every mismatched unit replaced by
- * U+FFFD (Sec. 1, Sec. 3.1). out == in runs in place (only changed 16-byte
- * groups are written); any other overlap is UTF16WF_EOVERLAP. Both pointers
- * must be 2-byte aligned; 16-byte alignment of `in` and equal alignment of
- * `in` and `out` modulo 16 select the fastest path. */
+ * U+FFFD (Sec. 1, Sec. 3.1). out == in runs in place (only the 128-byte
+ * lines that hold a changed unit are written); any other overlap is
+ * UTF16WF_EOVERLAP. Both pointers must be 2-byte aligned; any alignment runs
+ * with 16-byte loads and stores except at the two ends, unless `in` and
+ * `out` differ modulo 16 bytes: then the output is written unit by unit. */
 int utf16_to_well_formed(const uint16_t *in, uint16_t *out, int64_t n, void *stream);
 
 /* toWellFormed in place: same as utf16_to_well_formed(buf, buf, n, stream). */
