@@ -156,6 +156,69 @@ __device__ __forceinline__ u32x4 repair(u32x4 v, uint32_t badA, uint32_t badB) {
     return o;
 }
 
+// 16 bytes starting `sh` bytes (even, 2..14) into the 32 bytes a|b.
+__device__ __forceinline__ u32x4 realign(u32x4 a, u32x4 b, uint32_t sh) {
+    const uint32_t k = sh & 3u;  // 0 or 2: byte shift inside a dword
+    u32x4 o;
+    switch (sh >> 2) {
+    case 0:
+        o = (u32x4){__builtin_amdgcn_alignbyte(a.y, a.x, k), __builtin_amdgcn_alignbyte(a.z, a.y, k),
+                    __builtin_amdgcn_alignbyte(a.w, a.z, k), __builtin_amdgcn_alignbyte(b.x, a.w, k)};
+        break;
+    case 1:
+        o = (u32x4){__builtin_amdgcn_alignbyte(a.z, a.y, k), __builtin_amdgcn_alignbyte(a.w, a.z, k),
+                    __builtin_amdgcn_alignbyte(b.x, a.w, k), __builtin_amdgcn_alignbyte(b.y, b.x, k)};
+        break;
+    case 2:
+        o = (u32x4){__builtin_amdgcn_alignbyte(a.w, a.z, k), __builtin_amdgcn_alignbyte(b.x, a.w, k),
+                    __builtin_amdgcn_alignbyte(b.y, b.x, k), __builtin_amdgcn_alignbyte(b.z, b.y, k)};
+        break;
+    default:
+        o = (u32x4){__builtin_amdgcn_alignbyte(b.x, a.w, k), __builtin_amdgcn_alignbyte(b.y, b.x, k),
+                    __builtin_amdgcn_alignbyte(b.z, b.y, k), __builtin_amdgcn_alignbyte(b.w, b.z, k)};
+        break;
+    }
+    return o;
+}
+
+// Output whose address phase differs from the input's by ks units (1..7):
+// the 16-byte-aligned output vector a lane owns holds the last ks units of
+// the group before its own and the first 8 - ks of its own, so every store
+// is one aligned vector except the first 8 - ks units of a tile (`head`,
+// lane 0 of its first row) and its last ks units (`tail`, lane 63 of its
+// last row), which go unit by unit. o: the lane's repaired units
+// [u0, u0 + 8); pv: those of the group before (the lane before, or for
+// lane 0 the previous row's lane 63).
+template <bool NT>
+__device__ __forceinline__ void store_shifted(uint16_t *out, int64_t u0, int64_t lo, int64_t hi, u32x4 o, u32x4 pv,
+                                              uint32_t ks, bool head, bool tail) {
+    constexpr uint64_t kAll = 0x8080808080808080ull;
+    const int64_t c0 = u0 - (int64_t)ks;  // the aligned vector: units [c0, c0 + 8)
+    if (head) {
+        st_partial(out, u0, lo, hi, o, kAll & ((1ull << (8 * (8 - ks))) - 1));
+    } else {
+        const u32x4 c = realign(pv, o, 16u - 2u * ks);
+        if (c0 >= lo && c0 + 8 <= hi)
+            st16<NT>(out + c0, c);
+        else
+            st_partial(out, c0, lo, hi, c, kAll);
+    }
+    if (tail)
+        st_partial(out, u0, lo, hi, o, kAll & ~((1ull << (8 * (8 - ks))) - 1));
+}
+
+// The previous lane's vector (lane 0: `last`), and lane 63's, for
+// store_shifted. All lanes of the wave call these together.
+__device__ __forceinline__ u32x4 prev_lane(u32x4 o, u32x4 last, int lane) {
+    const u32x4 p = (u32x4){(uint32_t)__shfl_up((int)o.x, 1), (uint32_t)__shfl_up((int)o.y, 1),
+                            (uint32_t)__shfl_up((int)o.z, 1), (uint32_t)__shfl_up((int)o.w, 1)};
+    return lane == 0 ? last : p;
+}
+__device__ __forceinline__ u32x4 lane63(u32x4 o) {
+    return (u32x4){(uint32_t)__builtin_amdgcn_readlane((int)o.x, 63), (uint32_t)__builtin_amdgcn_readlane((int)o.y, 63),
+                   (uint32_t)__builtin_amdgcn_readlane((int)o.z, 63), (uint32_t)__builtin_amdgcn_readlane((int)o.w, 63)};
+}
+
 __device__ __forceinline__ bool is_high_unit(uint32_t u) { return (u & 0xFC00u) == 0xD800u; }
 __device__ __forceinline__ bool is_low_unit(uint32_t u) { return (u & 0xFC00u) == 0xDC00u; }
 
@@ -448,6 +511,10 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
             return;
     }
 
+    // output phase differing from the input's (SS): by ks units
+    const uint32_t ks = SS ? (uint32_t)((reinterpret_cast<uintptr_t>(out) & 15u) >> 1) : 0u;
+    u32x4 last = (u32x4){0u, 0u, 0u, 0u};  // SS: lane 63's repaired units of the previous row
+
     for (int64_t t = tb; t < te; ++t) {
         const int64_t tl = t * T, th = tl + T;
         if constexpr (OP == kOpIs && !BATCH) {
@@ -571,10 +638,15 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
 
             if constexpr (OP == kOpTo) {
                 const u32x4 o = wave_bad ? repair(v[r], badA, badB) : v[r];
-                if (interior && !SS)
+                if constexpr (SS) {
+                    store_shifted<NT>(out, u0, lo, hi, o, prev_lane(o, last, lane), ks, r == 0 && lane == 0,
+                                      r == R - 1 && lane == 63);
+                    last = lane63(o);
+                } else if (interior) {
                     st16<NT>(out + u0, o);
-                else
+                } else {
                     st_partial(out, u0, lo, hi, o, 0x8080808080808080ull);
+                }
             } else if constexpr (OP == kOpToInplace) {
                 // Inside the buffer, the eight lanes of a 128-byte line store
                 // together when any of them changed, so memory sees whole-line
@@ -770,6 +842,8 @@ __global__ void __launch_bounds__(1024) wf_multi_kernel(MultiArgs a) {
         if ((hl[R - 1] >> 63) && th < hi)
             carry_nx = is_low_unit(in[th]) ? 1ull : 0ull;
         const bool ss = a.s[i].scalar_store != 0;
+        const uint32_t ks = (uint32_t)((reinterpret_cast<uintptr_t>(out) & 15u) >> 1);
+        u32x4 last = (u32x4){0u, 0u, 0u, 0u};
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint64_t pm = (hl[r] << 1) | (r == 0 ? carry_in : (hl[r - 1] >> 63));
@@ -781,10 +855,15 @@ __global__ void __launch_bounds__(1024) wf_multi_kernel(MultiArgs a) {
             if constexpr (OP == kOpTo) {
                 const int64_t u0 = tl + ((int64_t)r * 64 + lane) * 8;
                 const u32x4 o = wave_bad ? repair(v[r], badA, badB) : v[r];
-                if (interior && !ss)
+                if (ss) {
+                    store_shifted<NT>(out, u0, lo, hi, o, prev_lane(o, last, lane), ks, r == 0 && lane == 0,
+                                      r == R - 1 && lane == 63);
+                    last = lane63(o);
+                } else if (interior) {
                     st16<NT>(out + u0, o);
-                else
+                } else {
                     st_partial(out, u0, lo, hi, o, 0x8080808080808080ull);
+                }
             } else {
                 if (wave_bad) {
                     if (lane == 0)
@@ -872,31 +951,6 @@ __global__ void validate_kernel(const int64_t *off, int64_t nstr, int64_t buf_un
         if (!ok)
             *bad = 1;
     }
-}
-
-// 16 bytes starting `sh` bytes (even, 2..14) into the 32 bytes a|b.
-__device__ __forceinline__ u32x4 realign(u32x4 a, u32x4 b, uint32_t sh) {
-    const uint32_t k = sh & 3u;  // 0 or 2: byte shift inside a dword
-    u32x4 o;
-    switch (sh >> 2) {
-    case 0:
-        o = (u32x4){__builtin_amdgcn_alignbyte(a.y, a.x, k), __builtin_amdgcn_alignbyte(a.z, a.y, k),
-                    __builtin_amdgcn_alignbyte(a.w, a.z, k), __builtin_amdgcn_alignbyte(b.x, a.w, k)};
-        break;
-    case 1:
-        o = (u32x4){__builtin_amdgcn_alignbyte(a.z, a.y, k), __builtin_amdgcn_alignbyte(a.w, a.z, k),
-                    __builtin_amdgcn_alignbyte(b.x, a.w, k), __builtin_amdgcn_alignbyte(b.y, b.x, k)};
-        break;
-    case 2:
-        o = (u32x4){__builtin_amdgcn_alignbyte(a.w, a.z, k), __builtin_amdgcn_alignbyte(b.x, a.w, k),
-                    __builtin_amdgcn_alignbyte(b.y, b.x, k), __builtin_amdgcn_alignbyte(b.z, b.y, k)};
-        break;
-    default:
-        o = (u32x4){__builtin_amdgcn_alignbyte(b.x, a.w, k), __builtin_amdgcn_alignbyte(b.y, b.x, k),
-                    __builtin_amdgcn_alignbyte(b.z, b.y, k), __builtin_amdgcn_alignbyte(b.w, b.z, k)};
-        break;
-    }
-    return o;
 }
 
 __device__ void copy_chunk(const CopyChunk &c);

@@ -106,6 +106,23 @@ def test_sizes_and_phases(wf, rows):
     wf.reset_params()
 
 
+@pytest.mark.parametrize("rows", ROWS)
+def test_every_output_phase(wf, rows):
+    """Output at every address phase against two input phases (all seven
+    relative shifts of the realigned stores, and equal phases), over several
+    tiles with partial ends, dense surrogates; nothing outside the output
+    range is written."""
+    _force_rows(wf, rows)
+    rng = np.random.default_rng(300 + rows)
+    alphabet = np.array([A, H, L, 0xDBFF, 0xDC00, 0x4E2D], np.uint16)
+    for n in (1, 7, 9, 3 * 512 * rows + 37, 5 * 512 * rows - 3):
+        s = alphabet[rng.integers(0, alphabet.size, size=n)]
+        for pi in (0, 3):
+            for po in range(8):
+                _check_all(wf, s, pi, po, what=f"n={n} rows={rows}")
+    wf.reset_params()
+
+
 PATTERNS = [[H], [L], [H, L], [L, H], [H, H, L], [H, L, L], [L, L], [H, H]]
 
 
