@@ -194,8 +194,9 @@ def per_string_vs_batched(torch, wf, stream, sample=20000):
 
 def zipf_tuned_vs_default(torch, wf, tune, stream):
     """The 4096-string Zipf(1.1) batch (up to 2^24 units per string): copy
-    repair, in-place repair and isWellFormed with early exit, each with the
-    autotuned launch shape and with the built-in default."""
+    repair, in-place repair and isWellFormed with early exit, each called
+    with its size hint, with the autotuned launch shape and with the built-in
+    default; and, tuned, without the hint (the shape for unknown sizes)."""
     from paper_2601_06349_amd import workloads as W
     buf, off, kind = W.zipf_batch()
     n = int(off[-1])
@@ -204,23 +205,27 @@ def zipf_tuned_vs_default(torch, wf, tune, stream):
     t_out = torch.empty_like(t_in)
     t_ip = torch.empty_like(t_in)
     res = torch.empty(off.size - 1, dtype=torch.uint8, device="cuda")
-    calls = {
-        "to": (lambda: wf.utf16_to_well_formed_batch(t_in, t_off, out=t_out), None, 4 * n),
-        "to_inplace": (lambda: wf.utf16_to_well_formed_batch_inplace(t_ip, t_off), lambda: t_ip.copy_(t_in),
-                       2 * n),
-        "is": (lambda: wf.utf16_is_well_formed_batch(t_in, t_off, results=res), None, 2 * n),
-    }
+    def calls(hint):
+        return {
+            "to": (lambda: wf.utf16wf_batch(wf.OP_TO, t_in, t_off, out=t_out, units_hint=hint), None, 4 * n),
+            "to_inplace": (lambda: wf.utf16wf_batch(wf.OP_TO_INPLACE, t_ip, t_off, out=t_ip, units_hint=hint),
+                           lambda: t_ip.copy_(t_in), 2 * n),
+            "is": (lambda: wf.utf16wf_batch(wf.OP_IS, t_in, t_off, results=res, units_hint=hint), None, 2 * n),
+        }
     lens = np.diff(off)
     ascii_units = int(lens[~kind].sum())
     out = {"workload": f"4096 strings, Zipf(1.1) lengths over 1..2^24, {n} units, "
                        f"{int(kind.sum())} strings mix(1e-2), the rest ({ascii_units} units) ASCII"}
-    for name, (fn, setup, algo_bytes) in calls.items():
+    unhinted = calls(0)
+    for name, (fn, setup, algo_bytes) in calls(n).items():
         wf.reset_params()
         d_ms, _ = time_fn(torch, stream, fn, reps=5, setup=setup)
         tune.apply_cache()
         t_ms, _ = time_fn(torch, stream, fn, reps=5, setup=setup)
+        u_ms, _ = time_fn(torch, stream, unhinted[name][0], reps=5, setup=setup)
         out[name] = {"default_ms": round(d_ms, 4), "tuned_ms": round(t_ms, 4),
-                     "tuned_input_GBps": round(2 * n / (t_ms * 1e-3) / 1e9, 1)}
+                     "tuned_input_GBps": round(2 * n / (t_ms * 1e-3) / 1e9, 1),
+                     "tuned_no_hint_ms": round(u_ms, 4)}
         if name == "is":
             # early exit: only the well-formed (ASCII) strings must be read whole
             out[name]["must_read_bytes"] = 2 * ascii_units
