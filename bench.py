@@ -122,7 +122,7 @@ def cpu_baseline(inputs, budget_s=12.0):
             if time.perf_counter() - t0 >= budget_s:
                 break
         passes += 1
-        if time.perf_counter() - t0 >= budget_s or passes >= 4:
+        if time.perf_counter() - t0 >= budget_s or passes >= 16:
             break
     el = time.perf_counter() - t0
     return {
