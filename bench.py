@@ -354,12 +354,12 @@ def host_resident(torch, wf, host_input):
 
 def profile_batches(torch, wf, W, reps=5):
     """Short run for rocprofv3 over the batch workloads, in a fixed order:
-    for the 1,000,000-string batch (with its size hint) and then the
-    4096-string Zipf batch (without), `reps` calls each of the out-of-place
-    repair, the check and the locate; then one copy-kernel launch over
-    268,435,456 units (the counters' calibration)."""
+    for the 1,000,000-string batch and then the 4096-string Zipf batch, each
+    with its size hint, `reps` calls each of the out-of-place repair, the
+    check and the locate; then one copy-kernel launch over 268,435,456 units
+    (the counters' calibration)."""
     for label, (buf, off), hinted in (("ragged 1M", W.ragged_batch(), True),
-                                      ("zipf 4096", W.zipf_batch()[:2], False)):
+                                      ("zipf 4096", W.zipf_batch()[:2], True)):
         log(f"profile: {label}")
         t_in = torch.from_numpy(buf.view(np.int16)).cuda()
         t_off = torch.from_numpy(off).cuda()
