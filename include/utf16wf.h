@@ -133,9 +133,11 @@ int utf16_locate_ill_formed_batch(const uint16_t *buf, const int64_t *offsets, i
 
 /* General batch entry used by the ones above. op is a UTF16WF_OP_* code;
  * results is used by OP_IS; first_bad/count by OP_LOCATE (pass NULL
- * otherwise). units_hint, if > 0, is an upper bound on
- * offsets[num_strings] - offsets[0] known to the caller; it only sizes the
- * launch (0 = unknown: a full persistent grid is launched). */
+ * otherwise). units_hint, if > 0, is the caller's figure for
+ * offsets[num_strings] - offsets[0]; it picks the tuned launch shape and
+ * grid size and, for OP_IS, whether a head pass over long strings runs
+ * first (0 = unknown: the shape for unknown sizes and a full persistent
+ * grid). Any value gives the same results; a wrong one only costs speed. */
 int utf16wf_batch(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets,
                   int64_t num_strings, uint8_t *results, int64_t *first_bad, int64_t *count,
                   int64_t units_hint, void *stream);

@@ -60,6 +60,60 @@ def test_caller_graph_capture_and_replay(wf):
         assert int(l[1]) == cnt and int(l[0]) == oracle.first_bad(cur), f"locate replay {rep}"
 
 
+def test_caller_graph_capture_of_batches(wf):
+    """Batch calls captured by a caller: the check of few long strings (its
+    head pass sets the results), the check with a size hint (a fill kernel
+    does), locate (one fill launch for both arrays) and the repair; every
+    replay, with new contents and eager work in between, equals the oracle."""
+    torch = torch_mod()
+    rng = np.random.default_rng(8)
+    lens = rng.integers(0, 40_000, size=40)
+    lens[:5] = [0, 1, 9000, 8191, 8192]
+    off = np.concatenate([[3], 3 + np.cumsum(lens)]).astype(np.int64)
+    base = W.mix(int(off[-1]) + 5, 2e-4, 32)
+    x = torch.from_numpy(base.view(np.int16)).cuda()
+    y = torch.zeros_like(x)
+    t_off = offsets_dev(off)
+    b = off.size - 1
+    r_head = torch.empty(b, dtype=torch.uint8, device="cuda")
+    r_fill = torch.empty(b, dtype=torch.uint8, device="cuda")
+    first = torch.empty(b, dtype=torch.int64, device="cuda")
+    count = torch.empty(b, dtype=torch.int64, device="cuda")
+    n_units = int(off[-1] - off[0])
+
+    def calls():
+        wf.utf16wf_batch(wf.OP_IS, x, t_off, results=r_head)  # no hint: head pass
+        wf.utf16wf_batch(wf.OP_IS, x, t_off, results=r_fill, units_hint=1)  # small hint: fill
+        wf.utf16wf_batch(wf.OP_LOCATE, x, t_off, first=first, count=count, units_hint=n_units)
+        wf.utf16wf_batch(wf.OP_TO, x, t_off, out=y, units_hint=n_units)
+
+    calls()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        calls()
+    for rep in range(5):
+        cur = base.copy()
+        if rep % 2:
+            cur = oracle.to_well_formed_batch(cur, off)  # every string well-formed
+        cur[rng.integers(off[0], off[-1], size=rep * 5)] = 0xD800
+        x.copy_(torch.from_numpy(cur.view(np.int16)))
+        y.zero_()
+        for t in (r_head, r_fill):
+            t.fill_(7)
+        first.fill_(-7)
+        count.fill_(-7)
+        g.replay()
+        torch.cuda.synchronize()
+        want_ok = oracle.is_well_formed_batch(cur, off)
+        assert np.array_equal(r_head.cpu().numpy(), want_ok), f"head-pass check, replay {rep}"
+        assert np.array_equal(r_fill.cpu().numpy(), want_ok), f"filled check, replay {rep}"
+        wf_first, wf_cnt = oracle.locate_batch(cur, off)
+        assert np.array_equal(first.cpu().numpy(), wf_first) and np.array_equal(count.cpu().numpy(), wf_cnt), \
+            f"locate, replay {rep}"
+        assert_same(to_host(y), oracle.to_well_formed_batch(cur, off, out=np.zeros_like(cur)), f"repair, replay {rep}")
+
+
 def test_concurrent_streams(wf):
     torch = torch_mod()
     streams = [torch.cuda.Stream() for _ in range(4)]
