@@ -1,8 +1,9 @@
 /*
  * utf16wf serving loop: continuous batching of UTF-16 repair requests on one
- * GPU. Not part of the paper (whose routine is a library call, Sec. 3); it
- * drives the ragged-batch entry of utf16wf.h, whose per-string semantics are
- * those of Sec. 1 and Sec. 3.1 applied to each request alone.
+ * GPU. Not part of the paper (whose routine is a library call, Sec. 3); each
+ * request is repaired or checked alone, with the semantics of Sec. 1 and
+ * Sec. 3.1, by the library's kernels for separate strings or for ragged
+ * batches (utf16wf.h).
  *
  * Requests arrive on a schedule (arrival times relative to the start of the
  * run). A request is admitted when the arena (one device allocation, the HBM
@@ -12,9 +13,9 @@
  * free up. Requests are admitted in arrival order (no reordering).
  *
  * A batch of at most 32 requests (separate_max) is one launch over the
- * requests where they lie, each a string of its own: the repair goes straight from the payload
- * to the destination (or into the batch's arena region when the request has
- * none). A larger batch is packed: each payload is copied into the batch's
+ * requests where they lie, each a string of its own: the repair goes
+ * straight from the payload to the destination (or into the batch's arena
+ * region when the request has none). A larger batch is packed: each payload is copied into the batch's
  * arena region, one ragged-batch launch repairs (or checks) it there, and
  * requests with a destination are copied out. Either way every request is
  * repaired alone, as one string.
@@ -60,7 +61,7 @@ typedef struct {
     int64_t done_ns;     /* when the host saw its batch complete (-1 if never) */
     int32_t status;      /* 0 done; UTF16WF_ERANGE larger than the arena;
                             UTF16WF_EHIP launch failure; 1 timed out */
-    int32_t batch;       /* batch index (-1 if never launched) */
+    int32_t batch;       /* batch index modulo 2^31 (-1 if never launched) */
     int32_t slot;        /* stream slot of its batch */
     int32_t well_formed; /* UTF16WF_OP_IS: 1 / 0; otherwise -1 */
 } utf16wf_serve_outcome;

@@ -218,7 +218,7 @@ class HipExec {
         if (cfg_.op == UTF16WF_OP_TO) {
             rc = strings_call(kOpTo, n, src, dst, len, nullptr, 0u, st);
         } else {
-            sl.stamp = (uint32_t)b.id + 1u;
+            sl.stamp = (uint32_t)(b.id + 1);  // never 0, the words' initial value, before 2^32 batches
             rc = strings_call(kOpIs, n, src, nullptr, len, sl.d_words, sl.stamp, st);
             if (rc == UTF16WF_OK &&
                 (e = hipMemcpyAsync(sl.h_words, sl.d_words, 4 * (size_t)n, hipMemcpyDeviceToHost, st)) != hipSuccess)

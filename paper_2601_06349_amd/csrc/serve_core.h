@@ -98,7 +98,7 @@ inline BatchLayout layout(int64_t nreq, int64_t units) {
 }
 
 struct Batch {
-    int32_t id = -1;
+    int64_t id = -1;
     int slot = -1;
     std::vector<int64_t> reqs;
     int64_t units = 0;
@@ -126,7 +126,7 @@ int run_loop(Exec &ex, const utf16wf_serve_config &cfg, const Request *rq, int64
     std::vector<Batch> inflight(slots);
     std::vector<bool> busy(slots, false);
     int64_t next = 0, finished = 0, nbusy = 0;
-    int32_t batch_id = 0;
+    int64_t batch_id = 0;
     utf16wf_serve_stats s{};
     for (int64_t i = 0; i < n; ++i)
         out[i] = utf16wf_serve_outcome{-1, -1, kStatusPending, -1, -1, cfg.op == UTF16WF_OP_IS ? 0 : -1};
@@ -209,7 +209,7 @@ int run_loop(Exec &ex, const utf16wf_serve_config &cfg, const Request *rq, int64
             const int rc = (b.region >= 0) ? ex.launch(b) : UTF16WF_ENOMEM;
             for (int64_t r : b.reqs) {
                 out[r].launch_ns = t;
-                out[r].batch = b.id;
+                out[r].batch = (int32_t)(b.id & 0x7FFFFFFF);  // (wraps past 2^31 batches)
                 out[r].slot = sl;
             }
             ++s.batches;
