@@ -204,9 +204,11 @@ def tune(quick=False, flat_classes=None, out=None, log=print):
     dev = {}
     for label, buf, off in (("zipf_4096", zb, zoff), ("ragged_1m", rb, roff)):
         t_in = torch.from_numpy(buf.view(np.int16)).cuda()
+        b = off.size - 1
         dev[label] = {"in": t_in, "off": torch.from_numpy(off).cuda(), "out": torch.empty_like(t_in),
-                      "ip": t_in.clone(), "res": torch.empty(off.size - 1, dtype=torch.uint8, device="cuda"),
-                      "units": int(off[-1])}
+                      "ip": t_in.clone(), "res": torch.empty(b, dtype=torch.uint8, device="cuda"),
+                      "first": torch.empty(b, dtype=torch.int64, device="cuda"),
+                      "count": torch.empty(b, dtype=torch.int64, device="cuda"), "units": int(off[-1])}
 
     def batch_call(label, op, hint):
         d = dev[label]
@@ -214,6 +216,9 @@ def tune(quick=False, flat_classes=None, out=None, log=print):
             return lambda: wf.utf16wf_batch(op, d["in"], d["off"], out=d["out"], units_hint=hint)
         if op == wf.OP_TO_INPLACE:
             return lambda: wf.utf16wf_batch(op, d["ip"], d["off"], out=d["ip"], units_hint=hint)
+        if op == wf.OP_LOCATE:
+            return lambda: wf.utf16wf_batch(op, d["in"], d["off"], first=d["first"], count=d["count"],
+                                            units_hint=hint)
         return lambda: wf.utf16wf_batch(op, d["in"], d["off"], results=d["res"], units_hint=hint)
 
     keys = [("zipf_4096", int(np.floor(np.log2(dev["zipf_4096"]["units"]))), [("zipf_4096", True)]),
@@ -221,7 +226,7 @@ def tune(quick=False, flat_classes=None, out=None, log=print):
             ("zipf_4096 + ragged_1m, no hint", 40, [("zipf_4096", False), ("ragged_1m", False)])]
     best_ms = {}  # (workload, op) -> its own tuned time, the targets of the no-hint class
     for label, cls, which in keys:
-        for op in (wf.OP_TO, wf.OP_TO_INPLACE, wf.OP_IS):
+        for op in (wf.OP_TO, wf.OP_TO_INPLACE, wf.OP_IS, wf.OP_LOCATE):
             calls = [batch_call(w, op, dev[w]["units"] if hinted else 0) for w, hinted in which]
             targets = [best_ms[(w, op)] for w, _ in which] if cls == 40 else None
             params, ms, dms = _sweep(wf, run, op, 1, cls, calls, 5, quick, targets=targets)
