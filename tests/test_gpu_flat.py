@@ -79,6 +79,20 @@ def test_fig3_example(wf):
         _check_all(wf, s, what=f"fig3@{off}")
 
 
+def test_readme_example(wf):
+    """The usage example in the README gives the values it states."""
+    torch = torch_mod()
+    s = torch.tensor([0x48, 0xD800, 0x69, 0xDC00], dtype=torch.uint16, device="cuda")
+    assert wf.utf16_to_well_formed(s).cpu().tolist() == [0x48, 0xFFFD, 0x69, 0xFFFD]
+    assert wf.is_well_formed(s) is False
+    buf = torch.tensor([0xD83D, 0xDE0A, 0xD83D, 0xDE0A], dtype=torch.uint16, device="cuda")
+    off = torch.tensor([0, 1, 4], dtype=torch.int64, device="cuda")
+    assert wf.utf16_to_well_formed_batch(buf, off).cpu().tolist() == [0xFFFD, 0xFFFD, 0xD83D, 0xDE0A]
+    res = torch.empty(2, dtype=torch.uint8, device="cuda")
+    wf.utf16wf_batch(wf.OP_IS, buf, off, results=res, units_hint=4)
+    assert res.cpu().tolist() == [0, 0]
+
+
 def test_small_workload(wf):
     s = W.small_string()
     log(f"small workload n={s.size}")
