@@ -318,6 +318,75 @@ def test_zipf_4096_full(wf):
     wf.reset_params()
 
 
+def test_batch_beyond_32bit_indices(wf):
+    """A batch over 2^31 + 2^21 + 5 units (4.3 GB): a string longer than 2^31
+    units, 100,001 short strings past unit 2^31 (so the many-strings path
+    runs on 64-bit offsets), mismatches planted inside them and across their
+    boundaries. Repair, check and locate are checked on windows against the
+    oracle and on every string's result; the same long string also goes
+    through the serving loop as one request (the separate-strings kernel)."""
+    torch = torch_mod()
+    from paper_2601_06349_amd import serve as S
+    G = 1 << 31
+    n = G + (1 << 21) + 5
+    small0 = G + 3000
+    off = np.concatenate([[0, 1000], small0 + 10 * np.arange(100_002), [n]]).astype(np.int64)
+    # string 1 = [1000, G + 3000): longer than 2^31 units
+    plants = {G + 1500: [L], 500: [H], small0 + 10 * 7 + 9: [H], small0 + 10 * 8: [L],  # cut pair
+              small0 + 10 * 500 + 4: [H, L], small0 + 10 * 900 + 4: [L, L], n - 1: [H]}
+    t = torch.full((n,), A, dtype=torch.int16, device="cuda")
+    for p, pat in plants.items():
+        t[p:p + len(pat)] = torch.tensor(np.array(pat, np.uint16).view(np.int16), device="cuda")
+    t_off = offsets_dev(off)
+    out = torch.full_like(t, 0x1234)
+    wf.utf16wf_batch(wf.OP_TO, t, t_off, out=out, units_hint=n)
+    b = off.size - 1
+    res = torch.empty(b, dtype=torch.uint8, device="cuda")
+    wf.utf16wf_batch(wf.OP_IS, t, t_off, results=res, units_hint=n)
+    first, count = wf.utf16_locate_ill_formed_batch(t, t_off)
+    res, first, count = res.cpu().numpy(), first.cpu().numpy(), count.cpu().numpy()
+    bad = set()
+    for p in plants:
+        a0, b0 = max(0, p - 40), min(n, p + 40)
+        win = to_host(t[a0:b0])
+        # the strings inside the window, clipped to it
+        ks = np.searchsorted(off, [a0, b0], side="right") - 1
+        cuts = np.unique(np.clip(off[max(ks[0], 0):min(ks[1] + 2, off.size)], a0, b0)) - a0
+        cuts = np.concatenate([[0], cuts[(cuts > 0) & (cuts < b0 - a0)], [b0 - a0]]).astype(np.int64)
+        w = oracle.to_well_formed_batch(win, cuts)
+        # a window end inside the buffer cuts a unit from its neighbour:
+        # compare the units that keep both
+        i0, i1 = (1 if a0 > 0 else 0), (b0 - a0) - (1 if b0 < n else 0)
+        assert_same(to_host(out[a0 + i0:a0 + i1]), w[i0:i1], f"repair window at {p}")
+        bad.update(int(u) for u in a0 + i0 + np.nonzero(w[i0:i1] != win[i0:i1])[0])
+    want_first = np.full(b, -1, np.int64)
+    want_count = np.zeros(b, np.int64)
+    for u in sorted(bad):
+        k = int(np.searchsorted(off, u, side="right") - 1)
+        want_count[k] += 1
+        if want_first[k] < 0:
+            want_first[k] = u - off[k]
+    assert len(bad) == 7  # the H, L pair is valid
+    assert np.array_equal(count, want_count) and np.array_equal(first, want_first)
+    assert np.array_equal(res, (want_count == 0).astype(np.uint8))
+    assert first[1] == G + 500  # a first index past 2^31 inside its string
+    # the long string as one served request (separate strings), into `out`
+    out.fill_(0x1234)
+    req = np.zeros(1, dtype=S.REQUEST_DTYPE)
+    req["src"] = t.data_ptr() + 2 * 1000
+    req["length"] = int(off[2] - off[1])
+    req["dst"] = out.data_ptr() + 2 * 1000
+    outc, st = S.run(req, S.make_config(num_streams=1, arena_bytes=12 << 30, max_batch_requests=1))
+    assert outc["status"][0] == 0 and st["direct_batches"] == 1
+    assert_same(to_host(out[G + 1492:G + 1508]), np.array([A] * 8 + [0xFFFD] + [A] * 7, np.uint16),
+                "served window")
+    assert_same(to_host(out[992:1008]), np.array([0x1234] * 8 + [A] * 8, np.uint16), "served start")
+    end = int(off[2])
+    assert_same(to_host(out[end - 8:end + 8]), np.array([A] * 8 + [0x1234] * 8, np.uint16), "served end")
+    del t, out
+    torch.cuda.empty_cache()
+
+
 def test_head_check_boundaries(wf):
     """Batches of few long strings get a head check of each string's first
     512 units: a pair across unit 511/512 is valid, a lone high at 511 is not,
