@@ -349,7 +349,8 @@ def host_resident(torch, wf, host_input):
             "first_two_calls_input_GBps": [round(2 * n / t / 1e9, 2) for t in first],
             "link_h2d_GBps": round(2 * n / h2d / 1e9, 2), "link_d2h_GBps": round(2 * n / d2h / 1e9, 2),
             "link_both_directions_GBps_each": round(2 * n / duplex / 1e9, 2),
-            "note": "pinned host in and out, 8 Mi-unit chunks, copies in on one stream, repair and copies out on another; includes both PCIe transfers"}
+            "note": "pinned host in and out, 8 Mi-unit chunks, copies in on one stream, repair and copies out "
+                    "on another; includes both PCIe transfers"}
 
 
 def profile_batches(torch, wf, W, reps=5):

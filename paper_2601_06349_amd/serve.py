@@ -69,7 +69,8 @@ def simulate(arrival_ns, lengths, config: ServeConfig, lat_base_ns=20_000, lat_n
 def latency_summary(outcomes, arrival_ns, lengths):
     """p50 / p99 / mean / max latency (ms) of completed requests, from their
     scheduled arrival to the host seeing their batch complete; throughput in
-    GB/s of input over the run; fraction of the run with at least one batch in flight (launch to completion seen by the host)."""
+    GB/s of input over the run; fraction of the run with at least one batch
+    in flight (launch to completion seen by the host)."""
     ok = outcomes["status"] == 0
     lat = (outcomes["done_ns"][ok] - np.asarray(arrival_ns)[ok]) / 1e6
     res = {"completed": int(ok.sum())}
