@@ -40,6 +40,31 @@ def test_every_declared_symbol_is_exported(L):
     assert set(names) <= set(_lib.SIGNATURES), "binding is missing a declared function"
 
 
+def test_headers_compile_as_c(tmp_path):
+    """The headers are a C ABI: they compile as C99 with warnings as errors,
+    and calls through them type-check."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use.c"
+    src.write_text(
+        '#include "utf16wf.h"\n#include "utf16wf_serve.h"\n'
+        "int use(const uint16_t *in, uint16_t *out, int64_t n, const int64_t *off, uint8_t *res, void *s) {\n"
+        "    utf16wf_params p;\n"
+        "    int rc = utf16_to_well_formed(in, out, n, s);\n"
+        "    rc |= utf16_is_well_formed_batch(in, off, 3, res, s);\n"
+        "    rc |= utf16wf_get_params(UTF16WF_OP_TO, 0, n, &p);\n"
+        "    utf16wf_serve_config c = {4, UTF16WF_OP_TO, 1 << 30, 64, 1 << 20, 0, 0};\n"
+        "    (void)c;\n"
+        "    return rc | utf16wf_abi_version();\n"
+        "}\n")
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic", "-I", HEADER_DIR, "-c",
+                        str(src), "-o", str(tmp_path / "use.o")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
 def test_abi_version(L):
     assert L.utf16wf_abi_version() == 1
 
