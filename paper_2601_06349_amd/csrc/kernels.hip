@@ -363,16 +363,27 @@ __device__ __forceinline__ uint32_t pack8(uint32_t fA, uint32_t fB) {
 // at or below p, found by shuffles; otherwise by a search in memory. The
 // check clears results[k]; the locate adds the lane's mismatches of one
 // string up before its atomics. All lanes of the wave call it together.
+// `last_goes_on`: the tile's last string (knext - 1) continues past the tile.
 template <int OP>
 __device__ __forceinline__ void resolve_strings(const KernelArgs &a, const int64_t *off, int64_t shift,
-                                                const TileStarts &ts, int64_t tl, int lane, uint64_t bits) {
+                                                const TileStarts &ts, int64_t tl, int lane, uint64_t bits,
+                                                bool last_goes_on) {
     int64_t cur_k = -1;
     uint64_t cur_first = 0, cur_count = 0;
     auto flush = [&]() {
         if (cur_k < 0)
             return;
         if constexpr (OP == kOpIs) {
-            __hip_atomic_store(a.results + cur_k, (uint8_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // Only the tile's last string can have units in tiles still to be
+            // read; its clearing is published device-wide for their skip test.
+            // A string that ends here is cleared through this XCD's cache,
+            // which the kernel's end writes back: device-coherent stores are
+            // slow to complete while the check streams reads, and one per
+            // string took the 4096-string Zipf check from 289 to 318 us.
+            if (last_goes_on && cur_k == ts.knext - 1)
+                __hip_atomic_store(a.results + cur_k, (uint8_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else
+                __hip_atomic_store(a.results + cur_k, (uint8_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         } else {
             atomicMin(reinterpret_cast<unsigned long long *>(a.first + cur_k), (unsigned long long)cur_first);
             atomicAdd(reinterpret_cast<unsigned long long *>(a.count + cur_k), (unsigned long long)cur_count);
@@ -676,14 +687,28 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
                         return;
                     }
                 } else if (single) {
-                    // The whole tile is string kc: one store settles it (and
-                    // none if another wave already did), and the tile's
-                    // remaining rows have nothing left to decide.
+                    // The whole tile is string kc: one store settles it, and
+                    // the tile's remaining rows have nothing left to decide.
+                    // All tiles of a long string are in flight together, so
+                    // when its errors are dense each of them finds one; if
+                    // every such wave published device-wide, thousands of
+                    // coherent stores to one byte would queue (a 16M-unit
+                    // string with errors past its head: 150 us instead of
+                    // 83). One wave in sixteen publishes (none if another
+                    // already did); the rest clear the byte through their
+                    // cache, which the kernel's end writes back.
                     if (wave_bad) {
-                        if (lane == 0 && __hip_atomic_load(a.results + ts.kc, __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT) != 0)
-                            __hip_atomic_store(a.results + ts.kc, (uint8_t)0, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+                        if (lane == 0) {
+                            if ((wave & 15) == 0) {
+                                if (__hip_atomic_load(a.results + ts.kc, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT) != 0)
+                                    __hip_atomic_store(a.results + ts.kc, (uint8_t)0, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                            } else {
+                                __hip_atomic_store(a.results + ts.kc, (uint8_t)0, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                            }
+                        }
                         break;
                     }
                 } else {
@@ -713,7 +738,7 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
         // group in row r, so a lane meets its units in increasing order.
         if constexpr (BATCH && (OP == kOpIs || OP == kOpLocate)) {
             if (!single && __ballot(bad_bits != 0ull))
-                resolve_strings<OP>(a, off, shift, ts, tl, lane, bad_bits);
+                resolve_strings<OP>(a, off, shift, ts, tl, lane, bad_bits, ts.onext > th);
         }
     }
 
@@ -866,8 +891,18 @@ __global__ void __launch_bounds__(1024) wf_multi_kernel(MultiArgs a) {
                 }
             } else {
                 if (wave_bad) {
-                    if (lane == 0)
-                        __hip_atomic_store(a.results + i, a.stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    // As in the batch check: the stamp is published device-
+                    // wide by one wave in sixteen, and only while the string
+                    // has tiles left for other waves to skip; the rest store
+                    // through their cache (a coherent store from every erring
+                    // tile of a long string queued on the one word and took
+                    // the serving loop's check p99 from 63 to 338 us).
+                    if (lane == 0) {
+                        if (th < hi && (wave & 15) == 0)
+                            __hip_atomic_store(a.results + i, a.stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        else
+                            __hip_atomic_store(a.results + i, a.stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
                     poll = a.stamp;
                     break;
                 }

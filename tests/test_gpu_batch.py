@@ -410,3 +410,60 @@ def test_head_check_boundaries(wf):
         _check_batch(wf, buf, off, what=f"head check hint={hint}", hint=hint)
     for phase in (1, 6):
         _check_batch(wf, buf, off, phase, phase, what=f"head check phase {phase}")
+
+
+def test_check_results_every_clearing_path(wf):
+    """Check results cleared by each kind of store: long strings with a clean
+    head whose later tiles all hold errors (many waves find them at once: one
+    in sixteen publishes the result device-wide, the rest clear it through
+    their cache), a single error late in a long string, short strings ending
+    inside a tile of several with an error at their end, and strings that go
+    on past such a tile with an error in it. The same results buffer then
+    serves a second batch in which those strings are well-formed: no cleared
+    byte of the first call may show in the second."""
+    torch = torch_mod()
+    rng = np.random.default_rng(11)
+    lens, kinds = [], []
+    for rep in range(3):
+        for n, kind in ((300_000, "dense"), (3, "end"), (250_000, "late"), (9000, "past_head"),
+                        (200_000, "dense"), (40_000, "first_tile")):
+            lens.append(n)
+            kinds.append(kind)
+        for _ in range(30):
+            lens.append(int(rng.integers(1, 300)))
+            kinds.append("end" if rng.random() < 0.5 else "clean")
+    lens = np.array(lens, np.int64)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    buf = W.ascii_units(int(off[-1]), 12)
+    for k, kind in enumerate(kinds):
+        s0, s1 = int(off[k]), int(off[k + 1])
+        if kind == "dense":
+            buf[s0 + 1000:s1:97] = L
+        elif kind == "end":
+            buf[s1 - 1] = H
+        elif kind == "late":
+            buf[s0 + (s1 - s0) * 4 // 5] = L
+        elif kind == "past_head":
+            buf[s0 + 600] = H
+        elif kind == "first_tile":
+            buf[s0 + 700] = L
+    fixed = oracle.to_well_formed_batch(buf, off)
+    t_off = offsets_dev(off)
+    b = off.size - 1
+    res = torch.empty(b, dtype=torch.uint8, device="cuda")
+    want1 = oracle.is_well_formed_batch(buf, off)
+    assert int((want1 == 0).sum()) > 50
+    want2 = oracle.is_well_formed_batch(fixed, off)
+    assert want2.all()
+    t1, _ = to_dev(buf, 0, pad=8)
+    t2, _ = to_dev(fixed, 0, pad=8)
+    for rows in ROWS:
+        for wg_waves, grid in ((4, 8), (1, 64)):
+            wf.set_params(wf.OP_IS, 1, -1, rows=rows, wg_waves=wg_waves, grid_per_cu=grid, nontemporal=0)
+            for hint in (0, int(off[-1])):
+                for t, want, what in ((t1, want1, "ill-formed"), (t2, want2, "repaired"), (t1, want1, "again")):
+                    wf.utf16wf_batch(wf.OP_IS, t, t_off, results=res, units_hint=hint)
+                    got = res.cpu().numpy()
+                    assert np.array_equal(got, want), \
+                        f"rows={rows} waves={wg_waves} grid={grid} hint={hint} {what}: {np.nonzero(got != want)[0][:10]}"
+    wf.reset_params()

@@ -208,6 +208,46 @@ def test_separate_strings_tile_edges(env, rows):
         wf.reset_params()
 
 
+def test_check_long_requests_every_clearing_path(env):
+    """Check requests run as separate strings: long payloads whose tiles past
+    the first all hold errors (many waves find them at once; one in sixteen
+    publishes the stamp device-wide, the rest store it through their cache),
+    one with a single error late, short ones; then, in the same run and on
+    the same slot, well-formed payloads of the same lengths, whose results
+    must not see the first batch's stamps."""
+    torch, S, wf = env["torch"], env["S"], env["wf"]
+    lens = [400_000, 300_000, 250_000, 5, 1000, 70_000]
+    bad_src = []
+    for i, n in enumerate(lens):
+        s = W.ascii_units(n, 50 + i)
+        if i in (0, 1):
+            s[5000::97] = 0xDC02
+        elif i == 2:
+            s[200_000] = 0xD801
+        elif i == 4:
+            s[-1] = 0xD801
+        bad_src.append(s)
+    srcs = bad_src + [oracle.to_well_formed(s) for s in bad_src]
+    d = torch.from_numpy(np.concatenate(srcs).view(np.int16)).cuda()
+    starts = np.concatenate([[0], np.cumsum([s.size for s in srcs])])[:-1]
+    reqs = np.zeros(len(srcs), dtype=S.REQUEST_DTYPE)
+    reqs["arrival_ns"] = [0] * len(lens) + [20_000_000] * len(lens)
+    reqs["src"] = np.uint64(d.data_ptr()) + 2 * starts.astype(np.uint64)
+    reqs["length"] = lens + lens
+    want = np.array([int(oracle.is_well_formed(s)) for s in srcs])
+    assert list(want) == [0, 0, 0, 1, 0, 1] + [1] * len(lens)
+    for rows in (1, 8):
+        wf.set_params(wf.OP_IS, 0, -1, rows=rows, wg_waves=4, grid_per_cu=8, nontemporal=0)
+        try:
+            out, st = S.run(reqs, S.make_config(num_streams=1, op=wf.OP_IS, arena_bytes=1 << 28,
+                                                max_batch_requests=32))
+        finally:
+            wf.reset_params()
+        assert np.all(out["status"] == 0) and st["direct_batches"] == st["batches"] == 2
+        assert np.array_equal(out["well_formed"], want), f"rows={rows}: {out['well_formed']} vs {want}"
+    del d
+
+
 def test_alone_launches_equal_oracle(env):
     """The same requests, one flat launch each (alone), equal the oracle."""
     torch, wf = env["torch"], env["wf"]
