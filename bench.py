@@ -533,6 +533,9 @@ def main():
         log("extras: serving loop, every batch packed (the ragged-batch path alone)")
         ex["serve_all_packed"] = S.serve_workload(duration_s=args.serve_seconds, rate_hz=50_000, num_streams=4,
                                                   arena_bytes=64 << 30, separate_max=-1, log=log)
+        log("extras: serving loop, isWellFormed requests")
+        ex["serve_check"] = S.serve_workload(duration_s=2.0, rate_hz=50_000, num_streams=4,
+                                             arena_bytes=64 << 30, op=wf.OP_IS, log=log)
         log("extras: the paper's 1024-unit strings, served")
         ex["paper_workloads"]["js_1024_served"] = S.serve_js_strings(duration_s=1.0, rate_hz=1_000_000, log=log)
         result["extras"] = ex

@@ -363,27 +363,22 @@ __device__ __forceinline__ uint32_t pack8(uint32_t fA, uint32_t fB) {
 // at or below p, found by shuffles; otherwise by a search in memory. The
 // check clears results[k]; the locate adds the lane's mismatches of one
 // string up before its atomics. All lanes of the wave call it together.
-// `last_goes_on`: the tile's last string (knext - 1) continues past the tile.
 template <int OP>
 __device__ __forceinline__ void resolve_strings(const KernelArgs &a, const int64_t *off, int64_t shift,
-                                                const TileStarts &ts, int64_t tl, int lane, uint64_t bits,
-                                                bool last_goes_on) {
+                                                const TileStarts &ts, int64_t tl, int lane, uint64_t bits) {
     int64_t cur_k = -1;
     uint64_t cur_first = 0, cur_count = 0;
     auto flush = [&]() {
         if (cur_k < 0)
             return;
         if constexpr (OP == kOpIs) {
-            // Only the tile's last string can have units in tiles still to be
-            // read; its clearing is published device-wide for their skip test.
-            // A string that ends here is cleared through this XCD's cache,
-            // which the kernel's end writes back: device-coherent stores are
-            // slow to complete while the check streams reads, and one per
-            // string took the 4096-string Zipf check from 289 to 318 us.
-            if (last_goes_on && cur_k == ts.knext - 1)
-                __hip_atomic_store(a.results + cur_k, (uint8_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            else
-                __hip_atomic_store(a.results + cur_k, (uint8_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            // Cleared through this XCD's cache; the kernel's end writes the
+            // byte back. Device-coherent stores into the few lines that hold
+            // the results are slow while the check streams reads: one per
+            // ill-formed string took the 4096-string Zipf check from 262 to
+            // 302 us, and publishing the clearing early buys little here
+            // (only a string's first tile holds other strings).
+            __hip_atomic_store(a.results + cur_k, (uint8_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         } else {
             atomicMin(reinterpret_cast<unsigned long long *>(a.first + cur_k), (unsigned long long)cur_first);
             atomicAdd(reinterpret_cast<unsigned long long *>(a.count + cur_k), (unsigned long long)cur_count);
@@ -473,6 +468,9 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
 
     uint32_t *bm = BATCH ? s_bm + wslot * kWords : nullptr;
     bool bm_dirty = true;  // LDS starts with arbitrary contents
+    // batch isWellFormed: string whose last tile this wave read was whole
+    // inside it and clean (-1 if none)
+    int64_t clean_k = -1;
     // batch: first string index of the wave's first tile. With many strings
     // the search is long and its result gates the tile's offsets scan, so it
     // runs first and the scan's loads then overlap the data loads; with few
@@ -615,6 +613,7 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
         // measured faster than classifying again there.)
         uint32_t hA_[R], hB_[R], lA_[R], lB_[R], sbits[R];
         uint64_t bad_bits = 0;  // batch check / locate: mismatches awaiting their string
+        bool tile_bad = false;  // batch check, whole-tile string: a mismatch was found
         uint64_t hl[R], lf[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -689,17 +688,22 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
                 } else if (single) {
                     // The whole tile is string kc: one store settles it, and
                     // the tile's remaining rows have nothing left to decide.
-                    // All tiles of a long string are in flight together, so
-                    // when its errors are dense each of them finds one; if
-                    // every such wave published device-wide, thousands of
-                    // coherent stores to one byte would queue (a 16M-unit
-                    // string with errors past its head: 150 us instead of
-                    // 83). One wave in sixteen publishes (none if another
-                    // already did); the rest clear the byte through their
-                    // cache, which the kernel's end writes back.
+                    // The clearing is published device-wide, for the skip
+                    // test of the string's tiles not yet read, only when this
+                    // wave found the string's previous tile clean: its errors
+                    // are then sparse and few waves publish. Where they are
+                    // dense every wave covering the string finds one in its
+                    // first tile, and their coherent stores would queue. On
+                    // 200 long strings with dense errors past their heads
+                    // the check took 128 us when every finder published and
+                    // 78 us under this rule; with one error late in each,
+                    // 270 us when none published and 208 us under it. Other
+                    // clearings go through this XCD's cache, which the
+                    // kernel's end writes back.
                     if (wave_bad) {
+                        tile_bad = true;
                         if (lane == 0) {
-                            if ((wave & 15) == 0) {
+                            if (skip_first && clean_k == ts.kc) {
                                 if (__hip_atomic_load(a.results + ts.kc, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT) != 0)
                                     __hip_atomic_store(a.results + ts.kc, (uint8_t)0, __ATOMIC_RELAXED,
@@ -736,9 +740,10 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
         // string of each mismatched unit, after the rows (their registers
         // are free by now). Bit 8r + j of bad_bits is unit j of the lane's
         // group in row r, so a lane meets its units in increasing order.
+        clean_k = (single && !tile_bad) ? ts.kc : -1;
         if constexpr (BATCH && (OP == kOpIs || OP == kOpLocate)) {
             if (!single && __ballot(bad_bits != 0ull))
-                resolve_strings<OP>(a, off, shift, ts, tl, lane, bad_bits, ts.onext > th);
+                resolve_strings<OP>(a, off, shift, ts, tl, lane, bad_bits);
         }
     }
 
@@ -891,12 +896,15 @@ __global__ void __launch_bounds__(1024) wf_multi_kernel(MultiArgs a) {
                 }
             } else {
                 if (wave_bad) {
-                    // As in the batch check: the stamp is published device-
-                    // wide by one wave in sixteen, and only while the string
-                    // has tiles left for other waves to skip; the rest store
-                    // through their cache (a coherent store from every erring
-                    // tile of a long string queued on the one word and took
-                    // the serving loop's check p99 from 63 to 338 us).
+                    // The stamp is published device-wide by one wave in
+                    // sixteen, and only while the string has tiles left for
+                    // other waves to skip; the rest store it through their
+                    // cache, which the kernel's end writes back. (A coherent
+                    // store from every erring tile of a long string queued
+                    // on the one word and took the serving loop's check p99
+                    // from 63 to 338 us. Waves here often hold one tile, so
+                    // the batch check's clean-previous-tile rule would
+                    // publish nothing.)
                     if (lane == 0) {
                         if (th < hi && (wave & 15) == 0)
                             __hip_atomic_store(a.results + i, a.stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -414,13 +414,14 @@ def test_head_check_boundaries(wf):
 
 def test_check_results_every_clearing_path(wf):
     """Check results cleared by each kind of store: long strings with a clean
-    head whose later tiles all hold errors (many waves find them at once: one
-    in sixteen publishes the result device-wide, the rest clear it through
-    their cache), a single error late in a long string, short strings ending
-    inside a tile of several with an error at their end, and strings that go
-    on past such a tile with an error in it. The same results buffer then
-    serves a second batch in which those strings are well-formed: no cleared
-    byte of the first call may show in the second."""
+    head whose later tiles all hold errors (many waves find them at once and
+    clear the result through their cache), a single error late in a long
+    string (published device-wide by the wave that read a clean tile of it
+    first), short strings ending inside a tile of several with an error at
+    their end, and strings that go on past such a tile with an error in it.
+    The same results buffer then serves a second batch in which those strings
+    are well-formed: no cleared byte of the first call may show in the
+    second."""
     torch = torch_mod()
     rng = np.random.default_rng(11)
     lens, kinds = [], []
