@@ -459,7 +459,10 @@ def test_check_results_every_clearing_path(wf):
     t1, _ = to_dev(buf, 0, pad=8)
     t2, _ = to_dev(fixed, 0, pad=8)
     for rows in ROWS:
-        for wg_waves, grid in ((4, 8), (1, 64)):
+        # many waves with a tile or two each, and few waves with long runs
+        # of tiles (where a wave reads a clean tile of a string before the
+        # erring one and publishes the clearing device-wide)
+        for wg_waves, grid in ((4, 8), (1, 64), (1, 1)):
             wf.set_params(wf.OP_IS, 1, -1, rows=rows, wg_waves=wg_waves, grid_per_cu=grid, nontemporal=0)
             for hint in (0, int(off[-1])):
                 for t, want, what in ((t1, want1, "ill-formed"), (t2, want2, "repaired"), (t1, want1, "again")):
