@@ -430,12 +430,18 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
     constexpr int kWords = 16 * R;
     constexpr bool kFlatLocate = (OP == kOpLocate && !BATCH);
     __shared__ uint32_t s_bm[BATCH ? kMaxWgWaves * kWords : 1];
-    // flat OP_LOCATE: per-workgroup totals, published by the last wave
-    __shared__ unsigned long long s_loc_first;
+    // OP_LOCATE: per-workgroup totals, published by the last wave (batch:
+    // for the one string s_loc_k that the first reporting wave names)
+    __shared__ unsigned long long s_loc_first, s_loc_k, s_loc_total;
     __shared__ uint32_t s_loc_count, s_loc_done;
-    if constexpr (kFlatLocate) {
+    // (batch: only with few strings, whose tiles span many workgroups; with
+    // many short ones each wave's last string is its own)
+    const bool loc_wg = kFlatLocate || (OP == kOpLocate && BATCH && a.nstr <= 65536);
+    if (loc_wg) {
         if (threadIdx.x == 0) {
             s_loc_first = ~0ull;
+            s_loc_k = ~0ull;
+            s_loc_total = 0ull;
             s_loc_count = 0u;
             s_loc_done = 0u;
         }
@@ -463,8 +469,8 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
     const int64_t per = (t1 - t0 + nwaves - 1) / nwaves;
     const int64_t tb = t0 + wave * per;
     const int64_t te = min(tb + per, t1);
-    if (tb >= te && !kFlatLocate)
-        return;  // (flat locate waves without tiles still report to their workgroup)
+    if (tb >= te && !loc_wg)
+        return;  // (such locate waves without tiles still report to their workgroup)
 
     uint32_t *bm = BATCH ? s_bm + wslot * kWords : nullptr;
     bool bm_dirty = true;  // LDS starts with arbitrary contents
@@ -747,9 +753,44 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
         }
     }
 
-    if constexpr (OP == kOpLocate && BATCH) {
+    if (OP == kOpLocate && BATCH && !loc_wg) {
         if (loc_k >= 0)
             loc_flush();
+    } else if (OP == kOpLocate && BATCH) {
+        // The string a wave ends on often spans the whole workgroup (a long
+        // string covers thousands of waves): such totals meet in LDS, and
+        // the workgroup's last wave adds them with one pair of atomics, not
+        // one pair per wave on the same two words (one 2^28-unit string
+        // with errors throughout: 241 -> 155 us; the Zipf batch of 4096
+        // strings: 498 -> 480 us).
+        uint32_t c = loc_count;
+#pragma unroll
+        for (int sh = 32; sh >= 1; sh >>= 1)
+            c += __shfl_xor(c, sh);
+        if (lane == 0) {
+            if (loc_k >= 0 && c != 0) {
+                const unsigned long long kk = (unsigned long long)loc_k;
+                const unsigned long long prev = atomicCAS(&s_loc_k, ~0ull, kk);
+                if (prev == ~0ull || prev == kk) {
+                    atomicAdd(&s_loc_total, (unsigned long long)c);
+                    atomicMin(&s_loc_first, (unsigned long long)loc_first);
+                } else {
+                    atomicAdd(reinterpret_cast<unsigned long long *>(a.count + loc_k), (unsigned long long)c);
+                    atomicMin(reinterpret_cast<unsigned long long *>(a.first + loc_k), (unsigned long long)loc_first);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (atomicAdd(&s_loc_done, 1u) == (uint32_t)wg_waves - 1u) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                const unsigned long long k = atomicCAS(&s_loc_k, ~0ull, ~0ull);
+                const unsigned long long tc = atomicAdd(&s_loc_total, 0ull);
+                const unsigned long long tf = atomicMin(&s_loc_first, ~0ull);
+                if (k != ~0ull && tc != 0) {
+                    atomicAdd(reinterpret_cast<unsigned long long *>(a.count + k), tc);
+                    atomicMin(reinterpret_cast<unsigned long long *>(a.first + k), tf);
+                }
+            }
+        }
     }
     if constexpr (kFlatLocate) {
         // wave totals -> workgroup totals in LDS -> one pair of global

@@ -471,3 +471,34 @@ def test_check_results_every_clearing_path(wf):
                     assert np.array_equal(got, want), \
                         f"rows={rows} waves={wg_waves} grid={grid} hint={hint} {what}: {np.nonzero(got != want)[0][:10]}"
     wf.reset_params()
+
+
+def test_locate_few_long_strings_workgroup_totals(wf):
+    """Locate over batches of few long strings with errors throughout: waves
+    that end on the same string add their totals in their workgroup first.
+    Shapes with more waves than tiles leave idle waves in a workgroup, which
+    must still report; a shape with one wave per workgroup has nothing to
+    combine."""
+    torch = torch_mod()
+    rng = np.random.default_rng(21)
+    cases = []
+    for lens in ([1_000_000], [700_000, 3, 900_001], [0, 250_000, 0, 250_000, 1], [5] * 40 + [600_000]):
+        lens = np.array(lens, np.int64)
+        off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+        buf = W.mix(int(off[-1]), 1e-2, int(rng.integers(1 << 30)))
+        cases.append((buf, off))
+    for rows, wg_waves, grid in ((4, 16, 64), (8, 4, 8), (1, 1, 32), (2, 16, 1)):
+        wf.set_params(wf.OP_LOCATE, 1, -1, rows=rows, wg_waves=wg_waves, grid_per_cu=grid, nontemporal=0)
+        for buf, off in cases:
+            t_in, _ = to_dev(buf, 0, pad=8)
+            t_off = offsets_dev(off)
+            b = off.size - 1
+            first = torch.empty(b, dtype=torch.int64, device="cuda")
+            cnt = torch.empty(b, dtype=torch.int64, device="cuda")
+            want_first, want_cnt = oracle.locate_batch(buf, off)
+            for hint in (0, int(off[-1])):
+                wf.utf16wf_batch(wf.OP_LOCATE, t_in, t_off, first=first, count=cnt, units_hint=hint)
+                what = f"rows={rows} waves={wg_waves} grid={grid} lens={np.diff(off)[:3]}.. hint={hint}"
+                assert np.array_equal(first.cpu().numpy(), want_first), f"first {what}"
+                assert np.array_equal(cnt.cpu().numpy(), want_cnt), f"count {what}"
+    wf.reset_params()
