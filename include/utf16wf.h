@@ -137,7 +137,9 @@ int utf16_locate_ill_formed_batch(const uint16_t *buf, const int64_t *offsets, i
  * offsets[num_strings] - offsets[0]; it picks the tuned launch shape and
  * grid size and, for OP_IS, whether a head pass over long strings runs
  * first (0 = unknown: the shape for unknown sizes and a full persistent
- * grid). Any value gives the same results; a wrong one only costs speed. */
+ * grid). Any value gives the same results; a wrong one only costs speed.
+ * OP_LOCATE over at most 256 strings takes the flat (batch 0) parameters of
+ * that size class, the shape for one long string. */
 int utf16wf_batch(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets,
                   int64_t num_strings, uint8_t *results, int64_t *first_bad, int64_t *count,
                   int64_t units_hint, void *stream);

@@ -29,6 +29,8 @@ def wf():
 def _force_rows(wf, rows, wg_waves=4, grid_per_cu=8, nt=0):
     for op in (wf.OP_IS, wf.OP_TO, wf.OP_TO_INPLACE, wf.OP_LOCATE):
         wf.set_params(op, 1, -1, rows=rows, wg_waves=wg_waves, grid_per_cu=grid_per_cu, nontemporal=nt)
+    # (a locate over few strings takes the flat parameters)
+    wf.set_params(wf.OP_LOCATE, 0, -1, rows=rows, wg_waves=wg_waves, grid_per_cu=grid_per_cu, nontemporal=nt)
 
 
 def _check_batch(wf, buf, off, phase_in=0, phase_out=0, what="", hint=0):
@@ -488,7 +490,8 @@ def test_locate_few_long_strings_workgroup_totals(wf):
         buf = W.mix(int(off[-1]), 1e-2, int(rng.integers(1 << 30)))
         cases.append((buf, off))
     for rows, wg_waves, grid in ((4, 16, 64), (8, 4, 8), (1, 1, 32), (2, 16, 1)):
-        wf.set_params(wf.OP_LOCATE, 1, -1, rows=rows, wg_waves=wg_waves, grid_per_cu=grid, nontemporal=0)
+        for batch in (0, 1):  # a locate over few strings takes the flat parameters
+            wf.set_params(wf.OP_LOCATE, batch, -1, rows=rows, wg_waves=wg_waves, grid_per_cu=grid, nontemporal=0)
         for buf, off in cases:
             t_in, _ = to_dev(buf, 0, pad=8)
             t_off = offsets_dev(off)
