@@ -229,10 +229,10 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // ------------------------------------------------------------ offsets
 
-// First index i in [0, len) with off[i] >= target, else len. All lanes of
-// the wave call it with the same arguments; probes 64 positions per round.
-__device__ int64_t lower_bound_wave(const int64_t *off, int64_t len, int64_t target, int lane) {
-    int64_t a = 0, b = len;  // the answer is in [a, b]
+// First index i in [a, b) with off[i] >= target, else b (off sorted). All
+// lanes of the wave call it with the same arguments; probes 64 positions per
+// round.
+__device__ int64_t lower_bound_wave(const int64_t *off, int64_t a, int64_t b, int64_t target, int lane) {
     while (b - a > 64) {
         const int64_t step = (b - a + 63) >> 6;
         const int64_t idx = a + (int64_t)lane * step;
@@ -319,6 +319,19 @@ __device__ __forceinline__ TileStarts scan_starts(const int64_t *off, int64_t ns
         inner = inner || (__ballot(o > tl && lt) != 0);
         const int c = __popcll(__ballot(lt));
         k += c;
+        if (c == 64) {
+            // 64 equal offsets: a run of empty strings, which may go on for
+            // millions; skip the rest of it with a search rather than reading
+            // it 64 at a time (its start bit is set, and a run at tl counts
+            // whole towards le)
+            const int64_t o0 = (int64_t)__shfl((long long)o, 0);
+            if (o0 == (int64_t)__shfl((long long)o, 63)) {
+                const int64_t kend = lower_bound_wave(off, k, nstr + 1, o0 - shift + 1, lane);
+                if (o0 <= tl)
+                    le += kend - k;
+                k = kend;
+            }
+        }
         if (c < 64) {
             window = first_round;
             onext = (int64_t)__shfl((long long)o, c);  // the first offset at or past th
@@ -486,7 +499,7 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
     int64_t cursor = -1;
     if constexpr (BATCH) {
         if (a.nstr > 65536)
-            cursor = lower_bound_wave(off, a.nstr + 1, tb * T - shift, lane);
+            cursor = lower_bound_wave(off, 0, a.nstr + 1, tb * T - shift, lane);
     }
 
     // OP_LOCATE accumulators: count per lane, first index per wave. Flat:
@@ -563,7 +576,7 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
                 ts = TileStarts{cursor - 1, cursor, cursor, nxt, (int32_t)T, true, nxt == th, false, false};
             } else {
                 if (cursor < 0)
-                    cursor = lower_bound_wave(off, a.nstr + 1, tl - shift, lane);
+                    cursor = lower_bound_wave(off, 0, a.nstr + 1, tl - shift, lane);
                 ts = scan_starts<R>(off, a.nstr, shift, cursor, tl, th, bm, lane, bm_dirty);
                 cursor = ts.knext;
                 nxt = ts.onext;
@@ -598,7 +611,7 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
         }
         if (BATCH && !skip_first) {
             if (cursor < 0)
-                cursor = lower_bound_wave(off, a.nstr + 1, tl - shift, lane);
+                cursor = lower_bound_wave(off, 0, a.nstr + 1, tl - shift, lane);
             ts = scan_starts<R>(off, a.nstr, shift, cursor, tl, th, bm, lane, bm_dirty);
             cursor = ts.knext;
         }

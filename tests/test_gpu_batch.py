@@ -505,3 +505,42 @@ def test_locate_few_long_strings_workgroup_totals(wf):
                 assert np.array_equal(first.cpu().numpy(), want_first), f"first {what}"
                 assert np.array_equal(cnt.cpu().numpy(), want_cnt), f"count {what}"
     wf.reset_params()
+
+
+def test_runs_of_empty_strings(wf):
+    """Runs of empty strings (equal offsets) of every length around the
+    64-offset scan step and far beyond it: at the batch's start, inside a
+    tile, at a tile edge, at the end, and between two runs; a run's position
+    belongs to the non-empty string after it."""
+    torch = torch_mod()
+    rng = np.random.default_rng(31)
+    n = 40_000
+    buf = W.mix(n, 2e-2, 17)
+    for rows in (1, 4):
+        T = 512 * rows
+        for run in (1, 63, 64, 65, 127, 128, 129, 1000, 200_000):
+            cuts = [0, 0, 700, T, 2 * T + 5, n // 2, n - 1, n, n]
+            offs = [0]
+            for c in cuts[1:]:
+                offs.extend([c] * (run if c in (0, T, n // 2, n) else 1))
+            offs.append(n)
+            off = np.array(sorted(offs), np.int64)
+            _force_rows(wf, rows)
+            _check_batch(wf, buf, off, what=f"runs of {run} empty, rows={rows}")
+            _check_batch(wf, buf, off, what=f"runs of {run} empty, rows={rows}, hinted", hint=n)
+    wf.reset_params()
+    # a run of a million empty strings before one long string, at full speed
+    big = W.mix(1 << 22, 1e-3, 18)
+    off = np.concatenate([np.zeros(1_000_000, np.int64), [0, big.size]]).astype(np.int64)
+    _check_batch(wf, big, off, what="1M empty strings first", hint=big.size)
+    t_in = to_dev(big, 0, pad=8)[0]
+    t_off = offsets_dev(off)
+    out = torch.empty_like(t_in)
+    torch.cuda.synchronize()
+    import time
+    t0 = time.perf_counter()
+    for _ in range(5):
+        wf.utf16wf_batch(wf.OP_TO, t_in, t_off, out=out, units_hint=big.size)
+    torch.cuda.synchronize()
+    per_call = (time.perf_counter() - t0) / 5
+    assert per_call < 2e-3, f"{per_call * 1e6:.0f} us per call: the run is read 64 offsets at a time"
