@@ -229,6 +229,14 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // ------------------------------------------------------------ offsets
 
+// The value of v in lane l (the same in every lane), read into scalar
+// registers.
+__device__ __forceinline__ int64_t lane_value(int64_t v, int l) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // First index i in [a, b) with off[i] >= target, else b (off sorted). All
 // lanes of the wave call it with the same arguments; probes 64 positions per
 // round.
@@ -324,8 +332,8 @@ __device__ __forceinline__ TileStarts scan_starts(const int64_t *off, int64_t ns
             // millions; skip the rest of it with a search rather than reading
             // it 64 at a time (its start bit is set, and a run at tl counts
             // whole towards le)
-            const int64_t o0 = (int64_t)__shfl((long long)o, 0);
-            if (o0 == (int64_t)__shfl((long long)o, 63)) {
+            const int64_t o0 = lane_value(o, 0), o63 = lane_value(o, 63);
+            if (o0 == o63) {
                 const int64_t kend = lower_bound_wave(off, k, nstr + 1, o0 - shift + 1, lane);
                 if (o0 <= tl)
                     le += kend - k;
