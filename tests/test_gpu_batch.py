@@ -544,3 +544,44 @@ def test_runs_of_empty_strings(wf):
     torch.cuda.synchronize()
     per_call = (time.perf_counter() - t0) / 5
     assert per_call < 2e-3, f"{per_call * 1e6:.0f} us per call: the run is read 64 offsets at a time"
+
+
+def test_random_shapes_and_contents(wf):
+    """Random launch shapes (rows, waves per workgroup, workgroups per CU,
+    non-temporal) against random batches: long and short strings, runs of
+    empty strings, error-free strings, strings with one late error and with
+    dense errors; every operation, with and without a size hint, against
+    the oracle."""
+    rng = np.random.default_rng(2026)
+    alphabet = np.array([A, 0x4E2D, H, L], np.uint16)
+    for case in range(24):
+        parts, lens = [], []
+        for _ in range(int(rng.integers(1, 40))):
+            kind = int(rng.integers(0, 6))
+            if kind == 0:    # a run of empty strings
+                lens.extend([0] * int(rng.choice([1, 63, 64, 65, 300])))
+                continue
+            n = int(rng.choice([1, 7, 100, 2048, 5000, 30_000, 120_000]))
+            s = np.full(n, A, np.uint16)
+            if kind == 1:    # random units, errors everywhere
+                s = alphabet[rng.integers(0, alphabet.size, size=n)].astype(np.uint16)
+            elif kind == 2:  # one error late
+                s[int(n * 0.9)] = H if rng.random() < 0.5 else L
+            elif kind == 3:  # dense errors past the first 600 units
+                s[600::97] = L
+            parts.append(s)
+            lens.append(n)
+        buf = np.concatenate(parts) if parts else np.full(1, A, np.uint16)
+        lens = np.array(lens, np.int64)
+        off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+        if off[-1] > buf.size:
+            buf = np.concatenate([buf, np.full(int(off[-1]) - buf.size, A, np.uint16)])
+        rows = int(rng.choice([1, 2, 4, 8]))
+        wg_waves = int(rng.choice([1, 2, 4, 8, 16]))
+        grid = int(rng.choice([1, 2, 8, 32, 64]))
+        nt = int(rng.integers(0, 2))
+        _force_rows(wf, rows, wg_waves, grid, nt)
+        hint = int(off[-1]) if case % 2 else 0
+        _check_batch(wf, buf, off, what=f"case {case} rows={rows} waves={wg_waves} grid={grid} nt={nt}",
+                     hint=hint)
+    wf.reset_params()
