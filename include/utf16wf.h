@@ -116,9 +116,12 @@ int utf16_is_well_formed_batch(const uint16_t *buf, const int64_t *offsets, int6
                                uint8_t *results, void *stream);
 
 /* toWellFormed per string into out, indexed by the same offsets (string k
- * goes to out[offsets[k], offsets[k+1])). out == in runs in place; any other
- * overlap of the two buffers is not allowed, and not checked (the span of
- * the batch is only known on the device). */
+ * goes to out[offsets[k], offsets[k+1])). out == in runs in place. Any other
+ * overlap of in[offsets[0], offsets[B]) with out[offsets[0], offsets[B]) is
+ * not allowed: the two ranges overlap exactly when in and out lie less than
+ * offsets[B] - offsets[0] units apart. That span is only known on the
+ * device, so this call cannot check it; utf16wf_batch with a size hint,
+ * plan creation and utf16wf_validate_batch return UTF16WF_EOVERLAP for it. */
 int utf16_to_well_formed_batch(const uint16_t *in, uint16_t *out, const int64_t *offsets,
                                int64_t num_strings, void *stream);
 
@@ -139,16 +142,29 @@ int utf16_locate_ill_formed_batch(const uint16_t *buf, const int64_t *offsets, i
  * first (0 = unknown: the shape for unknown sizes and a full persistent
  * grid). Any value gives the same results; a wrong one only costs speed.
  * OP_LOCATE over at most 256 strings takes the flat (batch 0) parameters of
- * that size class, the shape for one long string. */
+ * that size class, the shape for one long string.
+ * For UTF16WF_OP_TO with out != in and units_hint > 0, the hint is taken as
+ * the span: buffers less than 2 * units_hint bytes apart are rejected with
+ * UTF16WF_EOVERLAP before any HIP call. */
 int utf16wf_batch(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets,
                   int64_t num_strings, uint8_t *results, int64_t *first_bad, int64_t *count,
                   int64_t units_hint, void *stream);
 
 /* Checks offsets on the device: non-decreasing, offsets[0] >= 0 and
  * offsets[num_strings] <= buf_units. Synchronous on `stream`. Returns
- * UTF16WF_OK or UTF16WF_EOFFSETS. */
+ * UTF16WF_OK or UTF16WF_EOFFSETS. Uses a small device workspace that the
+ * library allocates on a device's first validation and keeps until the
+ * process ends. */
 int utf16wf_validate_offsets(const int64_t *offsets, int64_t num_strings, int64_t buf_units,
                              void *stream);
+
+/* Everything a batch call trusts its caller for: the offsets as in
+ * utf16wf_validate_offsets (UTF16WF_EOFFSETS), then, when out is neither
+ * NULL nor in, that in[offsets[0], offsets[B]) and out[offsets[0],
+ * offsets[B]) do not overlap (UTF16WF_EOVERLAP). Synchronous on `stream`;
+ * the same workspace as utf16wf_validate_offsets. */
+int utf16wf_validate_batch(const uint16_t *in, const uint16_t *out, const int64_t *offsets,
+                           int64_t num_strings, int64_t buf_units, void *stream);
 
 /* ---------------------------------------------------------- batch plans --- */
 /* A plan captures one batch call (its result initialisation and its
@@ -158,7 +174,9 @@ int utf16wf_validate_offsets(const int64_t *offsets, int64_t num_strings, int64_
  * creation the two ends of `offsets` are read on `stream` (which the call
  * synchronises; it must not be capturing) and the units they span size the
  * captured launch, as units_hint does for utf16wf_batch; offsets that change
- * later stay correct, the launch shape may only fit them less well. */
+ * later stay correct, the launch shape may only fit them less well. A
+ * UTF16WF_OP_TO plan whose out and in overlap over that span is rejected
+ * with UTF16WF_EOVERLAP. */
 int utf16wf_batch_plan_create(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets,
                               int64_t num_strings, uint8_t *results, void *stream, void **plan);
 int utf16wf_batch_plan_launch(void *plan, void *stream);

@@ -91,8 +91,11 @@ int utf16wf_serve_run(const utf16wf_serve_config *cfg, const utf16wf_serve_reque
 
 /* The same scheduler with a simulated executor and a virtual clock, no GPU:
  * a batch of U units completes lat_base_ns + lat_ns_per_unit * U after its
- * launch; if fail_every > 0, every fail_every-th batch fails at launch.
- * For capacity planning and for testing the scheduler on a CPU. */
+ * launch; if fail_every > 0, every fail_every-th batch fails at launch, after
+ * its work was queued (that work still occupies its arena region until it
+ * would have completed). For capacity planning and for testing the scheduler
+ * on a CPU. Returns UTF16WF_EHIP if the scheduler ever gave a batch an arena
+ * region that such queued work could still write. */
 int utf16wf_serve_simulate(const utf16wf_serve_config *cfg, const int64_t *arrival_ns, const int64_t *lengths,
                            int64_t n, int64_t lat_base_ns, double lat_ns_per_unit, int64_t fail_every,
                            utf16wf_serve_outcome *outcomes, utf16wf_serve_stats *stats);

@@ -41,13 +41,23 @@ def build() -> str:
     return _LIB
 
 
+def lib_path() -> str:
+    """The oracle library to load: the build named by UTF16WF_ORACLE_LIB if
+    set (the sanitizer test builds utf16_oracle.c with AddressSanitizer and
+    UBSan), else the plain build, compiled first if missing or stale."""
+    path = os.environ.get("UTF16WF_ORACLE_LIB")
+    if path:
+        return path
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    return _LIB
+
+
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        build()
-    lib = ctypes.CDLL(_LIB)
+    lib = ctypes.CDLL(lib_path())
     p16 = ctypes.c_void_p
     i64 = ctypes.c_int64
     lib.wf_to_seq.argtypes = [p16, p16, i64]

@@ -26,7 +26,7 @@ __all__ = [
     "utf16_is_well_formed", "utf16_to_well_formed", "utf16_to_well_formed_inplace",
     "utf16_locate_ill_formed", "utf16_to_well_formed_host", "utf16_is_well_formed_batch", "utf16_to_well_formed_batch",
     "utf16_to_well_formed_batch_inplace", "utf16_locate_ill_formed_batch", "utf16wf_batch",
-    "utf16wf_validate_offsets", "BatchPlan", "is_well_formed", "set_params", "get_params",
+    "utf16wf_validate_offsets", "utf16wf_validate_batch", "BatchPlan", "is_well_formed", "set_params", "get_params",
     "reset_params", "utf16wf_copy_units", "device_cus", "Utf16wfError", "lib", "last_error",
     "OP_IS", "OP_TO", "OP_TO_INPLACE", "OP_LOCATE", "OK", "EINVAL", "EALIGN", "EOVERLAP",
     "EOFFSETS", "EHIP", "ERANGE", "ENOMEM",
@@ -64,6 +64,32 @@ def _offsets(off):
     if off.numel() < 1:
         raise ValueError("offsets needs num_strings + 1 entries")
     return off
+
+
+def _same_device(name, t, ref):
+    if t.device != ref.device:
+        raise ValueError(f"{name} is on {t.device}, the input on {ref.device}")
+
+
+def _batch_out(out, buf):
+    """A caller's output buffer of a batch repair: code units on the input's
+    device, with room for every unit the offsets may name (those of buf)."""
+    _units(out, "out")
+    _same_device("out", out, buf)
+    if out.numel() < buf.numel():
+        raise ValueError(f"out has {out.numel()} units, fewer than the input's {buf.numel()}")
+    return out
+
+
+def _per_string(name, t, dtype, b, buf):
+    """A caller's per-string result array: at least b entries of dtype,
+    contiguous, on the input's device."""
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} device tensor")
+    _same_device(name, t, buf)
+    if t.numel() < b:
+        raise ValueError(f"{name} has {t.numel()} entries, fewer than the {b} strings")
+    return t
 
 
 def utf16_is_well_formed(t, result=None, stream=None):
@@ -133,9 +159,11 @@ def utf16_is_well_formed_batch(buf, offsets, results=None, stream=None):
     torch = _torch()
     _units(buf)
     _offsets(offsets)
+    _same_device("offsets", offsets, buf)
     b = offsets.numel() - 1
     if results is None:
         results = torch.empty(b, dtype=torch.uint8, device=buf.device)
+    _per_string("results", results, torch.uint8, b, buf)
     check(lib().utf16_is_well_formed_batch(buf.data_ptr(), offsets.data_ptr(), b, results.data_ptr(),
                                            _stream(stream)))
     return results
@@ -146,9 +174,10 @@ def utf16_to_well_formed_batch(buf, offsets, out=None, stream=None):
     written (a fresh ``out`` starts as a copy of ``buf``)."""
     _units(buf)
     _offsets(offsets)
+    _same_device("offsets", offsets, buf)
     if out is None:
         out = buf.clone()
-    _units(out, "out")
+    _batch_out(out, buf)
     check(lib().utf16_to_well_formed_batch(buf.data_ptr(), out.data_ptr(), offsets.data_ptr(),
                                            offsets.numel() - 1, _stream(stream)))
     return out
@@ -157,6 +186,7 @@ def utf16_to_well_formed_batch(buf, offsets, out=None, stream=None):
 def utf16_to_well_formed_batch_inplace(buf, offsets, stream=None):
     _units(buf)
     _offsets(offsets)
+    _same_device("offsets", offsets, buf)
     check(lib().utf16_to_well_formed_batch_inplace(buf.data_ptr(), offsets.data_ptr(), offsets.numel() - 1,
                                                    _stream(stream)))
     return buf
@@ -168,6 +198,7 @@ def utf16_locate_ill_formed_batch(buf, offsets, stream=None):
     torch = _torch()
     _units(buf)
     _offsets(offsets)
+    _same_device("offsets", offsets, buf)
     b = offsets.numel() - 1
     first = torch.empty(b, dtype=torch.int64, device=buf.device)
     count = torch.empty(b, dtype=torch.int64, device=buf.device)
@@ -178,11 +209,41 @@ def utf16_locate_ill_formed_batch(buf, offsets, stream=None):
 
 def utf16wf_batch(op, buf, offsets, out=None, results=None, first=None, count=None, units_hint=0, stream=None):
     """General batch entry (see the C header)."""
-    _units(buf)
-    _offsets(offsets)
+    _check_batch_buffers(op, buf, offsets, out, results, first, count)
     ptr = (lambda x: x.data_ptr() if x is not None else None)
     check(lib().utf16wf_batch(int(op), buf.data_ptr(), ptr(out), offsets.data_ptr(), offsets.numel() - 1,
                               ptr(results), ptr(first), ptr(count), int(units_hint), _stream(stream)))
+
+
+def _check_batch_buffers(op, buf, offsets, out=None, results=None, first=None, count=None):
+    """Every buffer a batch call of `op` writes is on the input's device and
+    large enough for the strings the offsets name."""
+    torch = _torch()
+    _units(buf)
+    _offsets(offsets)
+    _same_device("offsets", offsets, buf)
+    b = offsets.numel() - 1
+    if out is not None:
+        _batch_out(out, buf)
+    if op == OP_IS and results is not None:
+        _per_string("results", results, torch.uint8, b, buf)
+    if op == OP_LOCATE:
+        for name, t in (("first", first), ("count", count)):
+            if t is not None:
+                _per_string(name, t, torch.int64, b, buf)
+
+
+def utf16wf_validate_batch(buf, offsets, out=None, stream=None):
+    """Raises Utf16wfError(EOFFSETS) unless the offsets are non-decreasing
+    within [0, buf.numel()], and Utf16wfError(EOVERLAP) when ``out`` (neither
+    None nor ``buf``) overlaps ``buf`` over the units the batch spans.
+    Synchronises the stream."""
+    _units(buf)
+    _offsets(offsets)
+    if out is not None:
+        _units(out, "out")
+    check(lib().utf16wf_validate_batch(buf.data_ptr(), out.data_ptr() if out is not None else None,
+                                       offsets.data_ptr(), offsets.numel() - 1, buf.numel(), _stream(stream)))
 
 
 def utf16wf_validate_offsets(offsets, buf_units, stream=None):
@@ -196,8 +257,7 @@ class BatchPlan:
     """A batch call captured once into a HIP graph and replayed by launch()."""
 
     def __init__(self, op, buf, offsets, out=None, results=None, stream=None):
-        _units(buf)
-        _offsets(offsets)
+        _check_batch_buffers(op, buf, offsets, out, results)
         self._keep = (buf, offsets, out, results)  # keep the buffers alive
         h = ctypes.c_void_p()
         check(lib().utf16wf_batch_plan_create(

@@ -307,6 +307,13 @@ int batch_call(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets
         return fail(UTF16WF_EALIGN, "first_bad/count not 8-byte aligned");
     if (op == kOpTo && out == in)
         op = kOpToInplace;
+    // The units a batch spans are on the device; with a size hint they are
+    // known here: in[off[0], off[B]) and out[off[0], off[B]) overlap exactly
+    // when the two pointers lie less than that span apart.
+    if (op == kOpTo && units_hint > 0 && overlap_not_equal(in, out, units_hint))
+        return fail(UTF16WF_EOVERLAP, "input and output lie %lld bytes apart, closer than the %lld units the batch spans",
+                    (long long)(addr(in) > addr(out) ? addr(in) - addr(out) : addr(out) - addr(in)),
+                    (long long)units_hint);
 
     int dev, cus;
     if ((rc = current_device(&dev)) != UTF16WF_OK)
@@ -359,6 +366,46 @@ int batch_call(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets
     const LaunchShape sh = make_shape(p, cus, units_hint, 0);
     if ((e = launch_main(op, true, sh, a, stream)) != hipSuccess)
         return hip_fail(e, "kernel launch");
+    return UTF16WF_OK;
+}
+
+// Validation of a batch's offsets on the device (non-decreasing, within
+// [0, buf_units]); also returns offsets[0] and offsets[num_strings] in
+// ends. Synchronous on `stream`; the device flag is the per-device workspace.
+int validate_on_device(const int64_t *offsets, int64_t nstr, int64_t buf_units, hipStream_t s, int64_t ends[2]) {
+    int dev, rc;
+    if ((rc = current_device(&dev)) != UTF16WF_OK)
+        return rc;
+    Workspace *ws;
+    if ((rc = workspace(dev, &ws)) != UTF16WF_OK)
+        return rc;
+    // the device flag is shared by every validation on this device; the call
+    // is synchronous, so holding the lock for its duration serialises them
+    std::lock_guard<std::mutex> lk(g_validate_mu[dev]);
+    hipError_t e;
+    if ((e = launch_fill_i32(ws->flag, 0, 1, s)) != hipSuccess)
+        return hip_fail(e, "fill flag");
+    if ((e = launch_validate(offsets, nstr, buf_units, ws->flag, s)) != hipSuccess)
+        return hip_fail(e, "validate launch");
+    int32_t bad = 0;
+    if ((e = hipMemcpyAsync(&bad, ws->flag, sizeof bad, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&ends[0], offsets, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&ends[1], offsets + nstr, 8, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return hip_fail(e, "copy flag and offsets' ends");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, "synchronize");
+    if (bad)
+        return fail(UTF16WF_EOFFSETS, "offsets are not non-decreasing within [0, %lld]", (long long)buf_units);
+    return UTF16WF_OK;
+}
+
+// A batch repair into a distinct buffer whose span (offsets[B] - offsets[0]
+// units) is known: the two ranges it touches overlap exactly when the
+// buffers lie less than the span apart.
+int check_batch_overlap(const uint16_t *in, const uint16_t *out, int64_t span) {
+    if (out && out != in && overlap_not_equal(in, out, span))
+        return fail(UTF16WF_EOVERLAP, "input and output overlap over the %lld units the batch spans",
+                    (long long)span);
     return UTF16WF_OK;
 }
 
@@ -538,29 +585,25 @@ int utf16wf_validate_offsets(const int64_t *offsets, int64_t num_strings, int64_
         return fail(UTF16WF_EINVAL, "null offsets");
     if (addr(offsets) & 7u)
         return fail(UTF16WF_EALIGN, "offsets not 8-byte aligned");
-    int dev, rc;
-    if ((rc = current_device(&dev)) != UTF16WF_OK)
+    int64_t ends[2];
+    return validate_on_device(offsets, num_strings, buf_units, (hipStream_t)stream, ends);
+}
+
+int utf16wf_validate_batch(const uint16_t *in, const uint16_t *out, const int64_t *offsets, int64_t num_strings,
+                           int64_t buf_units, void *stream) {
+    if (num_strings < 0 || buf_units < 0)
+        return fail(UTF16WF_EINVAL, "negative size");
+    if (!in || !offsets)
+        return fail(UTF16WF_EINVAL, "null buffer or offsets");
+    int rc;
+    if ((rc = check_u16(in, "in")) != UTF16WF_OK || (out && (rc = check_u16(out, "out")) != UTF16WF_OK))
         return rc;
-    Workspace *ws;
-    if ((rc = workspace(dev, &ws)) != UTF16WF_OK)
+    if (addr(offsets) & 7u)
+        return fail(UTF16WF_EALIGN, "offsets not 8-byte aligned");
+    int64_t ends[2];
+    if ((rc = validate_on_device(offsets, num_strings, buf_units, (hipStream_t)stream, ends)) != UTF16WF_OK)
         return rc;
-    // the device flag is shared by every validation on this device; the call
-    // is synchronous, so holding the lock for its duration serialises them
-    std::lock_guard<std::mutex> lk(g_validate_mu[dev]);
-    hipStream_t s = (hipStream_t)stream;
-    hipError_t e;
-    if ((e = launch_fill_i32(ws->flag, 0, 1, s)) != hipSuccess)
-        return hip_fail(e, "fill flag");
-    if ((e = launch_validate(offsets, num_strings, buf_units, ws->flag, s)) != hipSuccess)
-        return hip_fail(e, "validate launch");
-    int32_t bad = 0;
-    if ((e = hipMemcpyAsync(&bad, ws->flag, sizeof bad, hipMemcpyDeviceToHost, s)) != hipSuccess)
-        return hip_fail(e, "copy flag");
-    if ((e = hipStreamSynchronize(s)) != hipSuccess)
-        return hip_fail(e, "synchronize");
-    if (bad)
-        return fail(UTF16WF_EOFFSETS, "offsets are not non-decreasing within [0, %lld]", (long long)buf_units);
-    return UTF16WF_OK;
+    return check_batch_overlap(in, out, ends[1] - ends[0]);
 }
 
 int utf16wf_batch_plan_create(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets,
@@ -607,6 +650,10 @@ int utf16wf_batch_plan_create(int op, const uint16_t *in, uint16_t *out, const i
             return hip_fail(e, "reading the offsets' ends");
         }
         units = std::max<int64_t>(0, ends[1] - ends[0]);
+        if (op == kOpTo && (rc = check_batch_overlap(in, out, units)) != UTF16WF_OK) {
+            delete p;
+            return rc;
+        }
     }
     hipStream_t cap;
     e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);

@@ -1,6 +1,6 @@
 // Serving loop on the GPU (include/utf16wf_serve.h): the scheduler of
-// serve_core.h driven by a HIP executor, and the same scheduler driven by a
-// simulated executor with a virtual clock.
+// serve_core.h driven by a HIP executor, and the same scheduler driven by the
+// simulated executor of serve_sim.h (virtual clock, no GPU).
 //
 // HIP executor, per batch on its slot's stream (default priority).
 // A batch of at most separate_max requests (at most kMultiMax) is one launch
@@ -32,6 +32,7 @@
 #include "internal.h"
 #include "kernels.h"
 #include "serve_core.h"
+#include "serve_sim.h"
 
 using namespace utf16wf;
 using namespace utf16wf::serve;
@@ -244,6 +245,8 @@ class HipExec {
         return -1;
     }
 
+    void drain(int slot) { (void)hipStreamSynchronize(slot_[slot].stream); }
+
     void finish(const Batch &b, utf16wf_serve_outcome *out) {
         if (cfg_.op != UTF16WF_OP_IS)
             return;
@@ -292,41 +295,6 @@ class HipExec {
     std::chrono::steady_clock::time_point t0_;
 };
 
-// ------------------------------------------------------ simulated executor
-
-class SimExec {
-  public:
-    SimExec(int slots, int64_t base, double per_unit, int64_t fail_every)
-        : done_at_(slots, 0), base_(base), per_unit_(per_unit), fail_every_(fail_every) {}
-    int64_t now() const { return t_; }
-    int launch(Batch &b) {
-        ++launches_;
-        if (fail_every_ > 0 && launches_ % fail_every_ == 0)
-            return set_error(UTF16WF_EHIP, "simulated launch failure");
-        done_at_[b.slot] = t_ + base_ + (int64_t)(per_unit_ * (double)b.units);
-        return UTF16WF_OK;
-    }
-    int done(int slot) { return t_ >= done_at_[slot] ? 1 : 0; }
-    void finish(const Batch &, utf16wf_serve_outcome *) {}
-    void idle(int64_t next_arrival, bool any_busy) {
-        int64_t t = INT64_MAX;
-        if (next_arrival >= 0)
-            t = next_arrival;
-        if (any_busy)
-            for (int64_t d : done_at_)
-                if (d > t_)
-                    t = std::min(t, d);
-        t_ = (t == INT64_MAX) ? t_ + 1 : std::max(t, t_ + 1);
-    }
-
-  private:
-    std::vector<int64_t> done_at_;
-    int64_t base_;
-    double per_unit_;
-    int64_t fail_every_;
-    int64_t t_ = 0, launches_ = 0;
-};
-
 }  // namespace
 
 extern "C" {
@@ -371,14 +339,18 @@ int utf16wf_serve_simulate(const utf16wf_serve_config *cfg, const int64_t *arriv
         return set_error(UTF16WF_EINVAL, "null arrays");
     if (lat_base_ns < 0 || lat_ns_per_unit < 0 || fail_every < 0)
         return set_error(UTF16WF_EINVAL, "negative latency model");
-    std::vector<Request> rq((size_t)n);
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t i = 0; i < n; ++i)
         if (lengths[i] < 0 || (i > 0 && arrival_ns[i] < arrival_ns[i - 1]))
             return set_error(UTF16WF_EINVAL, "negative length or decreasing arrivals");
-        rq[(size_t)i] = Request{arrival_ns[i], lengths[i]};
+    int64_t hazards = 0;
+    rc = simulate(*cfg, arrival_ns, lengths, n, lat_base_ns, lat_ns_per_unit, fail_every, outcomes, stats, &hazards);
+    if (rc == UTF16WF_OK && hazards > 0) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "simulation: %lld launches got an arena region that work queued by a failed launch "
+                 "could still write", (long long)hazards);
+        return set_error(UTF16WF_EHIP, buf);
     }
-    SimExec ex(cfg->num_streams, lat_base_ns, lat_ns_per_unit, fail_every);
-    return run_loop(ex, *cfg, rq.data(), n, outcomes, stats);
+    return rc;
 }
 
 }  // extern "C"

@@ -117,6 +117,8 @@ struct Request {
 //   int done(int slot);               // 1 when the slot's batch finished, 0 not yet, <0 failed
 //   void finish(const Batch &b, utf16wf_serve_outcome *out);
 //   void idle(int64_t next_arrival_ns /* -1 none */, bool any_busy);
+//   void drain(int slot);             // after a failed launch: wait for what it
+//                                     // queued on the slot before it failed
 template <class Exec>
 int run_loop(Exec &ex, const utf16wf_serve_config &cfg, const Request *rq, int64_t n,
              utf16wf_serve_outcome *out, utf16wf_serve_stats *st) {
@@ -221,8 +223,13 @@ int run_loop(Exec &ex, const utf16wf_serve_config &cfg, const Request *rq, int64
                 }
                 s.failed += (int64_t)b.reqs.size();
                 finished += (int64_t)b.reqs.size();
-                if (b.region >= 0)
+                if (b.region >= 0) {
+                    // a launch can fail after part of the batch (a copy, the
+                    // gather) is queued; that work may still write the region,
+                    // so it is freed only once the slot's queue has drained
+                    ex.drain(sl);
                     arena.release(b.region, b.lay.bytes);
+                }
                 continue;
             }
             inflight[sl] = std::move(b);

@@ -126,6 +126,73 @@ def test_batch_argument_errors(L):
     assert _rc(L, "utf16wf_validate_offsets", None, 3, 10, None) == EINVAL
     assert _rc(L, "utf16wf_validate_offsets", A + 4, 3, 10, None) == EALIGN
     assert _rc(L, "utf16wf_validate_offsets", A, -1, 10, None) == EINVAL
+    assert _rc(L, "utf16wf_validate_batch", None, A, A + 8192, 3, 10, None) == EINVAL
+    assert _rc(L, "utf16wf_validate_batch", A, A + 4096, None, 3, 10, None) == EINVAL
+    assert _rc(L, "utf16wf_validate_batch", A + 1, A + 4096, A + 8192, 3, 10, None) == EALIGN
+    assert _rc(L, "utf16wf_validate_batch", A, A + 4097, A + 8192, 3, 10, None) == EALIGN
+    assert _rc(L, "utf16wf_validate_batch", A, A + 4096, A + 8196, 3, 10, None) == EALIGN
+    assert _rc(L, "utf16wf_validate_batch", A, A + 4096, A + 8192, -1, 10, None) == EINVAL
+
+
+def test_batch_overlap_rejected_with_a_size_hint(L):
+    """A batch repair into a distinct buffer spans units_hint units when the
+    hint is given: buffers closer than that are rejected before any HIP call
+    (in either order, by one unit or by the whole span less one)."""
+    from paper_2601_06349_amd import EOVERLAP
+    span = 1000
+    for d in (2, 100, 2 * span - 2):
+        for i, o in ((A, A + d), (A + d, A)):
+            assert _rc(L, "utf16wf_batch", 1, i, o, A + 65536, 3, None, None, None, span, None) == EOVERLAP
+            assert "overlap" in L.utf16wf_last_error().decode() or "apart" in L.utf16wf_last_error().decode()
+
+
+class _FakeDeviceTensor:
+    """Stands in for a device tensor in the Python wrappers' argument checks,
+    which run before any library call (its pointer is never dereferenced)."""
+
+    def __init__(self, dtype, n, device="cuda:0", addr=A):
+        import torch
+        self.dtype, self._n, self.device, self._addr = dtype, n, torch.device(device), addr
+        self.is_cuda = True
+
+    def dim(self):
+        return 1
+
+    def is_contiguous(self):
+        return True
+
+    def numel(self):
+        return self._n
+
+    def data_ptr(self):
+        return self._addr
+
+
+def test_python_batch_wrappers_check_sizes_and_devices():
+    import torch
+    import paper_2601_06349_amd as wf
+    F = _FakeDeviceTensor
+    buf, off = F(torch.uint16, 1000), F(torch.int64, 11)  # 10 strings
+    with pytest.raises(ValueError, match="fewer than the input"):
+        wf.utf16_to_well_formed_batch(buf, off, out=F(torch.uint16, 999))
+    with pytest.raises(ValueError, match="fewer than the 10 strings"):
+        wf.utf16_is_well_formed_batch(buf, off, results=F(torch.uint8, 9))
+    with pytest.raises(TypeError):
+        wf.utf16_is_well_formed_batch(buf, off, results=F(torch.int32, 10))
+    with pytest.raises(ValueError, match="fewer than the 10 strings"):
+        wf.utf16wf_batch(wf.OP_LOCATE, buf, off, first=F(torch.int64, 10), count=F(torch.int64, 3))
+    with pytest.raises(ValueError, match="fewer than the 10 strings"):
+        wf.utf16wf_batch(wf.OP_IS, buf, off, results=F(torch.uint8, 2))
+    with pytest.raises(ValueError, match="fewer than the input"):
+        wf.utf16wf_batch(wf.OP_TO, buf, off, out=F(torch.uint16, 10))
+    with pytest.raises(ValueError, match="is on"):
+        wf.utf16wf_batch(wf.OP_TO, buf, off, out=F(torch.uint16, 1000, device="cuda:1"))
+    with pytest.raises(ValueError, match="is on"):
+        wf.utf16_to_well_formed_batch(buf, F(torch.int64, 11, device="cuda:1"))
+    with pytest.raises(ValueError, match="fewer than the input"):
+        wf.BatchPlan(wf.OP_TO, buf, off, out=F(torch.uint16, 5))
+    with pytest.raises(ValueError, match="fewer than the 10 strings"):
+        wf.BatchPlan(wf.OP_IS, buf, off, results=F(torch.uint8, 1))
 
 
 def test_plan_argument_errors(L):

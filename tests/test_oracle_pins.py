@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 @pytest.fixture(scope="module")
 def impl():
     oracle.build()
-    return P.OracleLib(oracle._LIB)
+    return P.OracleLib(oracle.lib_path())
 
 
 @pytest.mark.parametrize("pin", P.ALL_PINS, ids=lambda f: f.__name__)

@@ -184,3 +184,24 @@ def test_latency_summary():
     s = S.latency_summary(out, arr, lens)
     assert s["completed"] == 10 and abs(s["p50_ms"] - 0.5) < 1e-6 and abs(s["p99_ms"] - 0.5) < 1e-6
     assert 0.0 < s["inflight_frac"] <= 1.0
+
+
+def test_failed_launch_region_held_until_its_queued_work_drains():
+    """A launch that fails after part of its batch was queued (a copy, the
+    gather) must not hand its arena region to the next batch before that
+    work is done: the simulator queues a failing batch's work first and
+    reports any launch whose region such work could still write."""
+    n = 40
+    arr = np.zeros(n, dtype=np.int64)
+    lens = np.full(n, 20_000)
+    arena = 2 * _layout_bytes(1, 20_000)  # room for two batches: regions are reused at once
+    lat = 50_000
+    cfg = S.make_config(num_streams=2, arena_bytes=arena, max_batch_requests=1, max_batch_units=1 << 30)
+    out, st = S.simulate(arr, lens, cfg, lat_base_ns=lat, lat_ns_per_unit=0.0, fail_every=2)
+    assert st["failed"] == n // 2 and st["completed"] == n // 2
+    failed = np.nonzero(out["status"] == wf.EHIP)[0]
+    assert np.array_equal(failed, np.arange(1, n, 2))
+    # the batch after a failed one waits for the failed batch's queued work
+    for i in failed[failed + 1 < n]:
+        assert out["launch_ns"][i + 1] >= out["launch_ns"][i] + lat
+    assert st["arena_peak_bytes"] <= arena
