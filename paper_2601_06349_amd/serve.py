@@ -66,17 +66,29 @@ def simulate(arrival_ns, lengths, config: ServeConfig, lat_base_ns=20_000, lat_n
     return outcomes, st.as_dict()
 
 
-def latency_summary(outcomes, arrival_ns, lengths):
+def latency_summary(outcomes, arrival_ns, lengths, window_s=None):
     """p50 / p99 / mean / max latency (ms) of completed requests, from their
     scheduled arrival to the host seeing their batch complete; throughput in
     GB/s of input over the run; fraction of the run with at least one batch
-    in flight (launch to completion seen by the host)."""
+    in flight (launch to completion seen by the host). With window_s, also
+    p50 / p99 per window of that many seconds of arrivals (their spread shows
+    how much one run's tail varies)."""
     ok = outcomes["status"] == 0
     lat = (outcomes["done_ns"][ok] - np.asarray(arrival_ns)[ok]) / 1e6
     res = {"completed": int(ok.sum())}
     if lat.size:
         res.update(p50_ms=round(float(np.percentile(lat, 50)), 4), p99_ms=round(float(np.percentile(lat, 99)), 4),
                    mean_ms=round(float(lat.mean()), 4), max_ms=round(float(lat.max()), 4))
+        if window_s:
+            arr = np.asarray(arrival_ns)[ok]
+            win = (arr - arr.min()) // int(window_s * 1e9)
+            p50w, p99w = [], []
+            for w in range(int(win.max()) + 1):
+                x = lat[win == w]
+                if x.size:
+                    p50w.append(round(float(np.percentile(x, 50)), 4))
+                    p99w.append(round(float(np.percentile(x, 99)), 4))
+            res.update(window_s=window_s, p50_ms_by_window=p50w, p99_ms_by_window=p99w)
         t_end = float(outcomes["done_ns"][ok].max())
         t_start = float(np.asarray(arrival_ns)[ok].min())
         res["input_GBps"] = round(2.0 * float(np.asarray(lengths)[ok].sum()) / max(t_end - t_start, 1.0), 3)
@@ -101,7 +113,7 @@ def latency_summary(outcomes, arrival_ns, lengths):
 
 def serve_workload(duration_s=5.0, rate_hz=50_000.0, num_streams=4, arena_bytes=64 << 30,
                    max_batch_requests=4096, max_batch_units=1 << 26, op=OP_TO, seed=None,
-                   pool_len=1 << 24, n_pools=16, separate_max=0, log=None):
+                   pool_len=1 << 24, n_pools=16, separate_max=0, window_s=None, log=None):
     """The serving workload: Poisson arrivals at ``rate_hz`` for
     ``duration_s``, Zipf(1.1) lengths up to ``pool_len`` units, per-request
     lone-surrogate rate 10^U(-6,-1), payloads sliced from device-resident
@@ -126,41 +138,92 @@ def serve_workload(duration_s=5.0, rate_hz=50_000.0, num_streams=4, arena_bytes=
                       max_batch_requests=max_batch_requests, max_batch_units=max_batch_units,
                       separate_max=separate_max)
     out, st = run(reqs, cfg)
-    summ = latency_summary(out, sch["arrival_ns"], sch["length"])
+    summ = latency_summary(out, sch["arrival_ns"], sch["length"], window_s=window_s)
     summ.update({"requests": int(sch["length"].size), "duration_s": duration_s, "rate_hz": rate_hz,
+                 "seed": W.SEEDS["serve"] if seed is None else seed,
                  "num_streams": num_streams, "arena_bytes": arena_bytes, "separate_max": separate_max,
                  "stats": st})
     del d_pools
     return summ
 
 
-def serve_js_strings(duration_s=1.0, rate_hz=1_000_000.0, num_streams=4, arena_bytes=1 << 30,
-                     max_batch_requests=65536, n_distinct=4096, seed=1601, log=None):
-    """The paper's JavaScript shape served: Poisson arrivals of 1024-unit
-    strings with 5 % lone lows and 5 % lone highs (the rest ASCII), each a
-    copy of one of ``n_distinct`` device-resident strings. Returns a summary
-    dict."""
-    import torch
-
+def js_requests(duration_s=1.0, rate_hz=1_000_000.0, n_distinct=4096, seed=1601):
+    """The paper's JavaScript shape as a request stream: Poisson arrivals of
+    1024-unit strings with 5 % lone lows and 5 % lone highs (the rest
+    ASCII), each one of ``n_distinct`` strings. Returns (pool, arrival_ns,
+    which): the host pool of n_distinct * 1024 units, arrival times, and the
+    pool string of each request."""
     from . import workloads as W
     rng = np.random.default_rng(seed)
     pool = np.concatenate([W.js_string(seed=rng) for _ in range(n_distinct)])
-    d_pool = torch.from_numpy(pool.view(np.int16)).cuda()
     count = int(rng.poisson(rate_hz * duration_s))
     arrival = (np.cumsum(rng.exponential(1.0 / rate_hz, size=count)) * 1e9).astype(np.int64)
     which = rng.integers(0, n_distinct, size=count)
+    return pool, arrival, which
+
+
+def paper_1m_requests(duration_s=0.1, rate_hz=10_000.0, seed=1701):
+    """The paper's two 1,000,000-unit runs (0.1 % pairs; 0 % and 0.1 %
+    mismatched) as a request stream: Poisson arrivals, each request one of
+    the two strings. Returns (pool, arrival_ns, which): the host pool (the
+    two strings back to back), arrival times and each request's string."""
+    from . import workloads as W
+    rng = np.random.default_rng(seed)
+    pool = np.concatenate([W.paper_mix(1_000_000, 0.1, mis, W.SEEDS["paper_1m"]) for mis in (0.0, 0.1)])
+    count = int(rng.poisson(rate_hz * duration_s))
+    arrival = (np.cumsum(rng.exponential(1.0 / rate_hz, size=count)) * 1e9).astype(np.int64)
+    which = rng.integers(0, 2, size=count)
+    return pool, arrival, which
+
+
+def serve_fixed_length(pool, arrival, which, length, num_streams=4, arena_bytes=1 << 30,
+                       max_batch_requests=65536, dst=None, log=None, label=""):
+    """Serve requests that are each `length` units of the host `pool` at
+    string index `which[i]` (a device copy of the pool is made). With a
+    device `dst` tensor of len(which) * length units, request i repairs into
+    dst[i * length, (i + 1) * length). Returns a summary dict."""
+    import torch
+    d_pool = torch.from_numpy(pool.view(np.int16)).cuda()
+    count = which.size
     reqs = np.zeros(count, dtype=REQUEST_DTYPE)
     reqs["arrival_ns"] = arrival
-    reqs["src"] = np.uint64(d_pool.data_ptr()) + (2 * 1024 * which).astype(np.uint64)
-    reqs["length"] = 1024
+    reqs["src"] = np.uint64(d_pool.data_ptr()) + (2 * length * which).astype(np.uint64)
+    reqs["length"] = length
+    if dst is not None:
+        if dst.numel() < count * length:
+            raise ValueError("dst is smaller than the requests' outputs")
+        reqs["dst"] = np.uint64(dst.data_ptr()) + (2 * length * np.arange(count)).astype(np.uint64)
     if log:
-        log(f"serve js: {count} requests of 1024 units at {rate_hz:.0f}/s")
+        rate = count / max((arrival[-1] - arrival[0]) * 1e-9, 1e-9) if count > 1 else 0.0
+        log(f"serve {label}: {count} requests of {length} units at {rate:.0f}/s")
     torch.cuda.synchronize()
     cfg = make_config(num_streams=num_streams, op=OP_TO, arena_bytes=arena_bytes,
                       max_batch_requests=max_batch_requests, max_batch_units=1 << 26)
     out, st = run(reqs, cfg)
     summ = latency_summary(out, arrival, reqs["length"])
-    summ.update({"requests": count, "duration_s": duration_s, "rate_hz": rate_hz, "num_streams": num_streams,
-                 "stats": st})
+    summ.update({"requests": int(count), "num_streams": num_streams, "stats": st,
+                 "all_completed": bool(np.all(out["status"] == 0))})
     del d_pool
+    return summ
+
+
+def serve_js_strings(duration_s=1.0, rate_hz=1_000_000.0, num_streams=4, arena_bytes=1 << 30,
+                     max_batch_requests=65536, n_distinct=4096, seed=1601, dst=None, log=None):
+    """The paper's JavaScript shape served (js_requests); see
+    serve_fixed_length for `dst`. Returns a summary dict."""
+    pool, arrival, which = js_requests(duration_s, rate_hz, n_distinct, seed)
+    summ = serve_fixed_length(pool, arrival, which, 1024, num_streams=num_streams, arena_bytes=arena_bytes,
+                              max_batch_requests=max_batch_requests, dst=dst, log=log, label="js 1024")
+    summ.update({"duration_s": duration_s, "rate_hz": rate_hz})
+    return summ
+
+
+def serve_paper_1m(duration_s=0.1, rate_hz=10_000.0, num_streams=4, arena_bytes=4 << 30, seed=1701, dst=None,
+                   log=None):
+    """The paper's 1,000,000-unit runs served (paper_1m_requests); see
+    serve_fixed_length for `dst`. Returns a summary dict."""
+    pool, arrival, which = paper_1m_requests(duration_s, rate_hz, seed)
+    summ = serve_fixed_length(pool, arrival, which, 1_000_000, num_streams=num_streams, arena_bytes=arena_bytes,
+                              dst=dst, log=log, label="paper 1M")
+    summ.update({"duration_s": duration_s, "rate_hz": rate_hz})
     return summ

@@ -241,6 +241,38 @@ def js_string(n=1024, seed=SEEDS["js_1024"], low_pct=5.0, high_pct=5.0) -> np.nd
     return s.astype(np.uint16)
 
 
+PAPER_SWEEP_POINTS = 128
+
+
+def paper_sweep_sizes(points=PAPER_SWEEP_POINTS, top=1_000_000) -> np.ndarray:
+    """The size sweep of Sec. 4 (throughput from 0 to a million units): the
+    sizes top * k / points for k = 1..points."""
+    return (np.arange(1, points + 1, dtype=np.int64) * top) // points
+
+
+def paper_sweep_string(i: int, sizes=None) -> np.ndarray:
+    """A fresh string for sweep point i: the paper's generator at 0.1 %
+    pairs and 0.1 % mismatched, seeded per point."""
+    sizes = paper_sweep_sizes() if sizes is None else sizes
+    return paper_mix(int(sizes[i]), 0.1, 0.1, [SEEDS["paper_sweep"], int(i)])
+
+
+def paper_1m_batch(mis_pct: float, k=64):
+    """(buf, offsets): k strings of 1,000,000 units from the paper's
+    generator at 0.1 % pairs and mis_pct percent mismatched."""
+    buf = paper_mix(1_000_000 * k, 0.1, mis_pct, SEEDS["paper_1m"] + 1)
+    return buf, np.arange(0, 1_000_000 * (k + 1), 1_000_000, dtype=np.int64)
+
+
+def js_batch(k=1 << 18, distinct=64, seed=SEEDS["js_1024"] + 1):
+    """(buf, offsets): k JavaScript-shape strings of 1024 units, `distinct`
+    freshly drawn ones repeated in turn (distinct = k draws them all)."""
+    rng = _rng(seed)
+    one = np.concatenate([js_string(seed=rng) for _ in range(distinct)])
+    buf = np.tile(one, k // distinct) if k % distinct == 0 else np.resize(one, 1024 * k)
+    return buf, np.arange(0, 1024 * (k + 1), 1024, dtype=np.int64)
+
+
 def serve_schedule(duration_s: float, rate_hz=50_000.0, seed=SEEDS["serve"], max_len=1 << 24,
                    n_pools=16, pool_len=1 << 25, min_len=1):
     """Poisson arrival schedule for the serving loop.
