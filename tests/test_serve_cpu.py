@@ -205,3 +205,28 @@ def test_failed_launch_region_held_until_its_queued_work_drains():
     for i in failed[failed + 1 < n]:
         assert out["launch_ns"][i + 1] >= out["launch_ns"][i] + lat
     assert st["arena_peak_bytes"] <= arena
+
+
+def test_slice_expectations_equal_the_oracle_on_each_slice():
+    """The full serving test's expected outputs (the oracle over each pool,
+    with a slice's two end units from the oracle over those units alone)
+    equal the oracle run on each slice by itself."""
+    import oracle
+    from tests.test_gpu_serve import _slice_expectations
+    rng = np.random.default_rng(12)
+    pool_len = 4096
+    alphabet = np.array([0x41, 0xD800, 0xDBFF, 0xDC00, 0xDFFF, 0x4E2D], np.uint16)
+    pools_all = alphabet[rng.integers(0, alphabet.size, size=3 * pool_len)]
+    want_all = oracle.to_well_formed_batch(pools_all, np.arange(0, pools_all.size + 1, pool_len, dtype=np.int64))
+    k = 3000
+    p = rng.integers(0, 3, size=k)
+    lens = rng.integers(1, 40, size=k)
+    lens[:5] = [1, 2, 3, pool_len, pool_len - 1]
+    o = np.array([rng.integers(0, pool_len - ln + 1) for ln in lens])
+    o[3] = 0
+    g = p * pool_len + o
+    first, last = _slice_expectations(pools_all, g, lens)
+    for i in range(k):
+        want = want_all[g[i]:g[i] + lens[i]].copy()
+        want[0], want[-1] = first[i], last[i]
+        assert np.array_equal(want, oracle.to_well_formed(pools_all[g[i]:g[i] + lens[i]])), i
