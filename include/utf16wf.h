@@ -166,6 +166,22 @@ int utf16wf_validate_offsets(const int64_t *offsets, int64_t num_strings, int64_
 int utf16wf_validate_batch(const uint16_t *in, const uint16_t *out, const int64_t *offsets,
                            int64_t num_strings, int64_t buf_units, void *stream);
 
+/* For callers that cannot allocate device memory (code in tight serving
+ * loops, harnesses that forbid hipMalloc): utf16wf_validate_batch without
+ * the workspace that it allocates on a device's first call. Its flag lives
+ * in a 256-byte array of static device memory that every device the library
+ * runs on holds until the process ends (the validation uses 4 bytes of it,
+ * whatever the batch's size, so no batch is too large for it); the call
+ * allocates nothing, neither device nor pinned memory. Same arguments,
+ * checks, results and synchronisation as utf16wf_validate_batch. Every call
+ * on one device shares that device's array, which keeps the last call's
+ * contents (the flag is cleared by a kernel before each use): calls from
+ * this process on one device are serialised by the library, while
+ * validations that overlap on one device from several processes each use
+ * their own process's array. */
+int utf16wf_validate_batch_noalloc(const uint16_t *in, const uint16_t *out, const int64_t *offsets,
+                                   int64_t num_strings, int64_t buf_units, void *stream);
+
 /* ---------------------------------------------------------- batch plans --- */
 /* A plan captures one batch call (its result initialisation and its
  * persistent kernel) into a HIP graph once; launching replays the graph on

@@ -67,6 +67,7 @@ SIGNATURES = {
     "utf16wf_batch": (_INT, [_INT, _P, _P, _P, _I64, _P, _P, _P, _I64, _P]),
     "utf16wf_validate_offsets": (_INT, [_P, _I64, _I64, _P]),
     "utf16wf_validate_batch": (_INT, [_P, _P, _P, _I64, _I64, _P]),
+    "utf16wf_validate_batch_noalloc": (_INT, [_P, _P, _P, _I64, _I64, _P]),
     "utf16wf_batch_plan_create": (_INT, [_INT, _P, _P, _P, _I64, _P, _P, ctypes.POINTER(_P)]),
     "utf16wf_batch_plan_launch": (_INT, [_P, _P]),
     "utf16wf_batch_plan_destroy": (_INT, [_P]),

@@ -22,7 +22,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = [f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
-SOURCES = ["kernels.hip", "api.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "serve.cpp", "noalloc.hip"]
 
 
 def _compile(src: str) -> str:

@@ -369,36 +369,6 @@ int batch_call(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets
     return UTF16WF_OK;
 }
 
-// Validation of a batch's offsets on the device (non-decreasing, within
-// [0, buf_units]); also returns offsets[0] and offsets[num_strings] in
-// ends. Synchronous on `stream`; the device flag is the per-device workspace.
-int validate_on_device(const int64_t *offsets, int64_t nstr, int64_t buf_units, hipStream_t s, int64_t ends[2]) {
-    int dev, rc;
-    if ((rc = current_device(&dev)) != UTF16WF_OK)
-        return rc;
-    Workspace *ws;
-    if ((rc = workspace(dev, &ws)) != UTF16WF_OK)
-        return rc;
-    // the device flag is shared by every validation on this device; the call
-    // is synchronous, so holding the lock for its duration serialises them
-    std::lock_guard<std::mutex> lk(g_validate_mu[dev]);
-    hipError_t e;
-    if ((e = launch_fill_i32(ws->flag, 0, 1, s)) != hipSuccess)
-        return hip_fail(e, "fill flag");
-    if ((e = launch_validate(offsets, nstr, buf_units, ws->flag, s)) != hipSuccess)
-        return hip_fail(e, "validate launch");
-    int32_t bad = 0;
-    if ((e = hipMemcpyAsync(&bad, ws->flag, sizeof bad, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(&ends[0], offsets, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(&ends[1], offsets + nstr, 8, hipMemcpyDeviceToHost, s)) != hipSuccess)
-        return hip_fail(e, "copy flag and offsets' ends");
-    if ((e = hipStreamSynchronize(s)) != hipSuccess)
-        return hip_fail(e, "synchronize");
-    if (bad)
-        return fail(UTF16WF_EOFFSETS, "offsets are not non-decreasing within [0, %lld]", (long long)buf_units);
-    return UTF16WF_OK;
-}
-
 // A batch repair into a distinct buffer whose span (offsets[B] - offsets[0]
 // units) is known: the two ranges it touches overlap exactly when the
 // buffers lie less than the span apart.
@@ -412,6 +382,48 @@ int check_batch_overlap(const uint16_t *in, const uint16_t *out, int64_t span) {
 }  // namespace
 
 namespace utf16wf {
+
+int validation_flag_on_device(const int64_t *offsets, int64_t nstr, int64_t buf_units, hipStream_t s,
+                              int32_t *flag, int64_t ends[2]) {
+    hipError_t e;
+    if ((e = launch_fill_i32(flag, 0, 1, s)) != hipSuccess)
+        return hip_fail(e, "fill flag");
+    if ((e = launch_validate(offsets, nstr, buf_units, flag, s)) != hipSuccess)
+        return hip_fail(e, "validate launch");
+    int32_t bad = 0;
+    if ((e = hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&ends[0], offsets, 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&ends[1], offsets + nstr, 8, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return hip_fail(e, "copy flag and offsets' ends");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, "synchronize");
+    if (bad)
+        return fail(UTF16WF_EOFFSETS, "offsets are not non-decreasing within [0, %lld]", (long long)buf_units);
+    return UTF16WF_OK;
+}
+
+int check_validate_batch_args(const uint16_t *in, const uint16_t *out, const int64_t *offsets, int64_t nstr,
+                              int64_t buf_units) {
+    if (nstr < 0 || buf_units < 0)
+        return fail(UTF16WF_EINVAL, "negative size");
+    if (!in || !offsets)
+        return fail(UTF16WF_EINVAL, "null buffer or offsets");
+    int rc;
+    if ((rc = check_u16(in, "in")) != UTF16WF_OK || (out && (rc = check_u16(out, "out")) != UTF16WF_OK))
+        return rc;
+    if (addr(offsets) & 7u)
+        return fail(UTF16WF_EALIGN, "offsets not 8-byte aligned");
+    return UTF16WF_OK;
+}
+
+int validate_batch_with(const uint16_t *in, const uint16_t *out, const int64_t *offsets, int64_t nstr,
+                        int64_t buf_units, hipStream_t s, int32_t *flag) {
+    int64_t ends[2];
+    int rc = validation_flag_on_device(offsets, nstr, buf_units, s, flag, ends);
+    if (rc != UTF16WF_OK)
+        return rc;
+    return check_batch_overlap(in, out, ends[1] - ends[0]);
+}
 
 int set_error(int code, const char *msg) {
     g_err = msg;
@@ -585,25 +597,28 @@ int utf16wf_validate_offsets(const int64_t *offsets, int64_t num_strings, int64_
         return fail(UTF16WF_EINVAL, "null offsets");
     if (addr(offsets) & 7u)
         return fail(UTF16WF_EALIGN, "offsets not 8-byte aligned");
+    int dev, rc;
+    Workspace *ws;
+    if ((rc = current_device(&dev)) != UTF16WF_OK || (rc = workspace(dev, &ws)) != UTF16WF_OK)
+        return rc;
+    // the device flag is shared by every validation on this device; the call
+    // is synchronous, so holding the lock for its duration serialises them
+    std::lock_guard<std::mutex> lk(g_validate_mu[dev]);
     int64_t ends[2];
-    return validate_on_device(offsets, num_strings, buf_units, (hipStream_t)stream, ends);
+    return validation_flag_on_device(offsets, num_strings, buf_units, (hipStream_t)stream, ws->flag, ends);
 }
 
 int utf16wf_validate_batch(const uint16_t *in, const uint16_t *out, const int64_t *offsets, int64_t num_strings,
                            int64_t buf_units, void *stream) {
-    if (num_strings < 0 || buf_units < 0)
-        return fail(UTF16WF_EINVAL, "negative size");
-    if (!in || !offsets)
-        return fail(UTF16WF_EINVAL, "null buffer or offsets");
-    int rc;
-    if ((rc = check_u16(in, "in")) != UTF16WF_OK || (out && (rc = check_u16(out, "out")) != UTF16WF_OK))
+    int rc = check_validate_batch_args(in, out, offsets, num_strings, buf_units);
+    if (rc != UTF16WF_OK)
         return rc;
-    if (addr(offsets) & 7u)
-        return fail(UTF16WF_EALIGN, "offsets not 8-byte aligned");
-    int64_t ends[2];
-    if ((rc = validate_on_device(offsets, num_strings, buf_units, (hipStream_t)stream, ends)) != UTF16WF_OK)
+    int dev;
+    Workspace *ws;
+    if ((rc = current_device(&dev)) != UTF16WF_OK || (rc = workspace(dev, &ws)) != UTF16WF_OK)
         return rc;
-    return check_batch_overlap(in, out, ends[1] - ends[0]);
+    std::lock_guard<std::mutex> lk(g_validate_mu[dev]);
+    return validate_batch_with(in, out, offsets, num_strings, buf_units, (hipStream_t)stream, ws->flag);
 }
 
 int utf16wf_batch_plan_create(int op, const uint16_t *in, uint16_t *out, const int64_t *offsets,

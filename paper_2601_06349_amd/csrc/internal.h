@@ -22,4 +22,14 @@ int set_error(int code, const char *msg);
 int strings_call(int op, int n, const uint16_t *const *src, uint16_t *const *dst, const int64_t *len,
                  uint32_t *results, uint32_t stamp, hipStream_t stream);
 
+// Batch validation as utf16wf_validate_batch does it, with the device int32
+// `flag` supplied by the caller (who keeps other validations off it until
+// the call returns): check_validate_batch_args makes the argument checks
+// (no HIP call); validate_batch_with then checks the offsets on the device
+// and the overlap of in and out over the span they give. Synchronous on s.
+int check_validate_batch_args(const uint16_t *in, const uint16_t *out, const int64_t *offsets, int64_t nstr,
+                              int64_t buf_units);
+int validate_batch_with(const uint16_t *in, const uint16_t *out, const int64_t *offsets, int64_t nstr,
+                        int64_t buf_units, hipStream_t s, int32_t *flag);
+
 }  // namespace utf16wf
