@@ -28,10 +28,14 @@
 //     variant).
 //   * No loop-carried state between tiles (Sec. 3.1 discussion), so waves
 //     take contiguous runs of tiles and never communicate.
-//   * Ragged batches mark string starts in a per-wave LDS bitmap, filled from
-//     the offsets that fall inside the tile; a start cuts the pairing between
-//     a unit and its predecessor. The check and the locate find the string
-//     of a mismatch among the tile's offsets, which stay in the wave's lanes.
+//   * Ragged batches: the repair marks string starts in a per-wave LDS
+//     bitmap, filled from the offsets that fall inside the tile; a start cuts
+//     the pairing between a unit and its predecessor. The check and the
+//     locate keep all rows of a lane in one set of flag words (row r at bit
+//     7 - r of each byte), compute the mismatches of the whole tile as if it
+//     were one string, and let each lane of the tile's offsets take one
+//     string: it tests its own range of units, and the pairs its two ends
+//     cut (span_planes).
 //   * Up to 32 separate strings, each at its own address (a serving batch),
 //     run in one launch: each string is tiled alone, as a flat call's frame.
 #include "kernels.h"
@@ -258,44 +262,27 @@ __device__ int64_t lower_bound_wave(const int64_t *off, int64_t a, int64_t b, in
     return a + __popcll(__ballot(lt));
 }
 
-// Last k in [a, b) with off[k] + shift <= p (requires off[a] + shift <= p),
-// clamped to a valid string index below nstr.
-__device__ __forceinline__ int64_t string_of(const int64_t *off, int64_t shift, int64_t a, int64_t b,
-                                             int64_t p, int64_t nstr) {
-    a = min(max(a, (int64_t)0), nstr - 1);
-    b = min(b, nstr);
-    while (b - a > 1) {
-        const int64_t m = (a + b) >> 1;
-        if (off[m] + shift <= p)
-            a = m;
-        else
-            b = m;
-    }
-    return a;
-}
-
 struct TileStarts {
     int64_t kc;     // string holding unit tl (-1 if tl is before the first string)
     int64_t knext;  // first k with off[k] + shift >= th
     int64_t k0;     // first k with off[k] + shift >= tl (the scan's cursor)
     int64_t onext;  // off[knext] + shift (INT64_MAX past the last offset)
-    int32_t orel;   // window: min(off[k0 + lane] + shift - tl, tile units)
-    bool window;    // every start of the tile, and the first one past it, sit in orel
     bool next;      // a string starts at unit th
     bool inner;     // a string starts in (tl, th)
     bool any;       // a string starts in [tl, th) (the bitmap has a bit set)
+    bool at_tl = false;  // a string starts at unit tl
 };
 
 // Marks the string starts in [tl, th) in the wave's bitmap (bit u - tl).
 // `cursor` is the first k with off[k] + shift >= tl. The bitmap is cleared
 // only when the previous tile left bits in it (`dirty`), so tiles inside one
 // long string touch no LDS at all.
-template <int R>
+template <int R, bool BITMAP = true>
 __device__ __forceinline__ TileStarts scan_starts(const int64_t *off, int64_t nstr, int64_t shift,
                                                   int64_t cursor, int64_t tl, int64_t th, uint32_t *bm,
-                                                  int lane, bool &dirty) {
+                                                  int lane, bool &dirty, int64_t *o_first = nullptr) {
     constexpr int kWords = 16 * R;
-    if (dirty) {
+    if (BITMAP && dirty) {
 #pragma unroll
         for (int i = 0; i < (kWords + 63) / 64; ++i) {
             const int w = i * 64 + lane;
@@ -306,16 +293,15 @@ __device__ __forceinline__ TileStarts scan_starts(const int64_t *off, int64_t ns
         dirty = false;
     }
     int64_t k = cursor, le = 0;
-    bool next = false, inner = false, first_round = true, window = false;
-    int32_t orel = 0;
+    bool next = false, inner = false, first_round = true;
     int64_t onext = INT64_MAX;
     for (;;) {
         const int64_t idx = k + lane;
         const int64_t o = idx <= nstr ? off[idx] + shift : INT64_MAX;
-        if (first_round)
-            orel = o < tl ? 0 : (int32_t)min(o - tl, (int64_t)(kRowUnits * R));
+        if (first_round && o_first)
+            *o_first = o;
         const bool lt = o < th;
-        if (lt) {
+        if (BITMAP && lt) {
             // with valid offsets tl <= o < th always holds here; the test
             // keeps malformed offsets from writing outside the bitmap
             const int64_t rel = o - tl;
@@ -341,106 +327,143 @@ __device__ __forceinline__ TileStarts scan_starts(const int64_t *off, int64_t ns
             }
         }
         if (c < 64) {
-            window = first_round;
             onext = (int64_t)__shfl((long long)o, c);  // the first offset at or past th
             break;
         }
         first_round = false;
     }
-    const bool any = k != cursor;
+    const bool any = BITMAP && k != cursor;
     if (any) {
         wave_lds_sync();
         dirty = true;
     }
-    return TileStarts{cursor + le - 1, k, cursor, onext, orel, window, next, inner, any};
+    TileStarts ts{cursor + le - 1, k, cursor, onext, next, inner, any};
+    ts.at_tl = le > 0;
+    return ts;
 }
 
-// Number of lanes whose `orel` is <= p, for sorted `orel` with lane 63 above
-// every p asked (a tile's offsets window): a binary search over the lanes by
-// shuffles, six steps. All lanes of the wave must call it together.
-__device__ __forceinline__ int lanes_le(int32_t orel, int32_t p) {
-    int pos = 0;
+// Bits of the 64-bit group mask m (row r of a tile: group 64 r + lane) that
+// lie in groups [g0, g1].
+__device__ __forceinline__ uint64_t groups_in(uint64_t m, int r, int g0, int g1) {
+    const int lo = max(g0 - 64 * r, 0), hi = min(g1 - 64 * r, 63);
+    if (lo > hi)
+        return 0ull;
+    const uint64_t upto = hi == 63 ? ~0ull : ((2ull << hi) - 1ull);
+    return m & upto & ~((1ull << lo) - 1ull);
+}
+
+// Batch check and locate of a tile that holds string starts. The tile's
+// mismatches and pairs were computed as in one string (a pair across a string
+// start counts as a pair) for all rows at once: w4[lane] holds the lane's
+// mismatch flags (x: units 0..3, y: units 4..7) and pair flags (z, w: the
+// unit is a low after a high), unit j of row r at bit 8 (j & 3) + 7 - r;
+// M[r] has bit `lane` set where the lane's row-r units hold a mismatch. Each
+// lane takes one string: lane j of a round of 64 offsets (offsets kb + j)
+// takes string kb + j - 1, whose units in the tile are [max(a, tl), min(o,
+// th)) with a = offsets[kb + j - 1] and o = offsets[kb + j] (plus shift). Its
+// mismatches are the ones in that range, plus a pair cut by its start (the
+// unit at a is a low after a high) or by its end (the unit at o is) when that
+// boundary lies inside the tile; boundaries at tl and th were cut when the
+// tile was computed. The check clears the string's result; the locate adds
+// its count and offers its first mismatch. o_first: offsets[cursor + lane]
+// + shift (INT64_MAX past the last), cursor the first k with offsets[k] +
+// shift >= tl. start_prev: where string cursor - 1 starts, if known
+// (INT64_MIN otherwise; the locate then reads it). Returns the start of the
+// string holding unit th - 1, if known. All lanes of the wave call it
+// together.
+template <int OP, int R>
+__device__ __forceinline__ int64_t span_planes(const KernelArgs &a, const int64_t *off, int64_t shift,
+                                               int64_t cursor, int64_t o_first, int64_t tl, int64_t th, int lane,
+                                               const uint4 *w4, const uint64_t (&M)[R], int64_t start_prev) {
+    constexpr int T = kRowUnits * R;
+    constexpr uint64_t kUnits = 0x0101010101010101ull;  // bit 8 j: unit j of row 7
+    int64_t kb = cursor, o = o_first;
+    int32_t ac = -1;               // start of string kb - 1 relative to tl (-1: before the tile)
+    int64_t ac_abs = start_prev;   // ... and absolute, if known
+    for (;;) {
+        const int32_t orl = (int32_t)min(max(o - tl, (int64_t)-1), (int64_t)T + 1);
+        int32_t arl = __shfl_up(orl, 1);
+        if (lane == 0)
+            arl = ac;
+        const int64_t k = kb + lane - 1;
+        const int64_t o63 = lane_value(o, 63);
+        if (k >= 0 && k < a.nstr && orl > 0 && arl < T && arl < orl) {
+            const int ul = max(arl, 0), uh = min(orl, T);
+            const int g0 = ul >> 3, g1 = (uh - 1) >> 3;
+            const uint4 W0 = w4[g0 & 63], W1 = w4[g1 & 63];
+            const uint64_t from0 = ~0ull << (8 * (ul & 7));        // units >= ul in its group
+            const uint64_t upto1 = ~0ull >> (56 - 8 * ((uh - 1) & 7));  // units < uh in its group
+            const uint64_t row0 = kUnits << (7 - (g0 >> 6)), row1 = kUnits << (7 - (g1 >> 6));
+            const uint64_t bad0 = ((uint64_t)W0.y << 32 | W0.x) & row0 & from0;
+            const uint64_t f0 = g0 == g1 ? bad0 & upto1 : bad0;
+            const uint64_t f1 = g0 == g1 ? 0ull : ((uint64_t)W1.y << 32 | W1.x) & row1 & upto1;
+            const uint64_t p0 = (uint64_t)W0.w << 32 | W0.z;
+            const bool cs = arl > 0 && ((p0 >> (8 * (ul & 7) + 7 - (g0 >> 6))) & 1ull);
+            bool ce = false;
+            if (orl < T) {
+                const int ge = uh >> 3;
+                const uint4 We = w4[ge & 63];
+                ce = ((((uint64_t)We.w << 32 | We.z) >> (8 * (uh & 7) + 7 - (ge >> 6))) & 1ull) != 0ull;
+            }
+            if constexpr (OP == kOpIs) {
+                bool bad = cs || ce || f0 || f1;
+                if (!bad && g1 - g0 >= 2) {
 #pragma unroll
-    for (int step = 32; step >= 1; step >>= 1) {
-        const int32_t v = __shfl(orel, pos + step - 1);
-        if (v <= p)
-            pos += step;
-    }
-    return pos;
-}
-
-// The flags of a lane's 8 units (bit 7 of each byte of A = units 0..3, B =
-// units 4..7) as 8 bits, bit j = unit j.
-__device__ __forceinline__ uint32_t pack8(uint32_t fA, uint32_t fB) {
-    const uint32_t a = (((fA >> 7) & 0x01010101u) * 0x01020408u) >> 24;
-    const uint32_t b = (((fB >> 7) & 0x01010101u) * 0x01020408u) >> 24;
-    return a | (b << 4);
-}
-
-// Batch check / locate of a tile that holds several strings: bit 8r + j of
-// `bits` marks a mismatch at unit tl + (64 r + lane) 8 + j. Each one is
-// charged to its string (the last k with off[k] + shift <= p): with the
-// tile's offsets in the lanes (ts.window), k = k0 - 1 + the number of them
-// at or below p, found by shuffles; otherwise by a search in memory. The
-// check clears results[k]; the locate adds the lane's mismatches of one
-// string up before its atomics. All lanes of the wave call it together.
-template <int OP>
-__device__ __forceinline__ void resolve_strings(const KernelArgs &a, const int64_t *off, int64_t shift,
-                                                const TileStarts &ts, int64_t tl, int lane, uint64_t bits) {
-    int64_t cur_k = -1;
-    uint64_t cur_first = 0, cur_count = 0;
-    auto flush = [&]() {
-        if (cur_k < 0)
-            return;
-        if constexpr (OP == kOpIs) {
-            // Cleared through this XCD's cache; the kernel's end writes the
-            // byte back. Device-coherent stores into the few lines that hold
-            // the results are slow while the check streams reads: one per
-            // ill-formed string took the 4096-string Zipf check from 262 to
-            // 302 us, and publishing the clearing early buys little here
-            // (only a string's first tile holds other strings).
-            __hip_atomic_store(a.results + cur_k, (uint8_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        } else {
-            atomicMin(reinterpret_cast<unsigned long long *>(a.first + cur_k), (unsigned long long)cur_first);
-            atomicAdd(reinterpret_cast<unsigned long long *>(a.count + cur_k), (unsigned long long)cur_count);
-        }
-    };
-    // p: the unit; k: its string; start: where that string begins
-    auto charge = [&](int64_t p, int64_t k, int64_t start) {
-        if (k != cur_k) {
-            flush();
-            cur_k = k;
-            cur_first = (uint64_t)(p - start);
-            cur_count = 0;
-        }
-        ++cur_count;
-    };
-    if (ts.window) {
-        while (__ballot(bits != 0ull)) {
-            const int b = bits ? __builtin_ctzll(bits) : 0;
-            const int pr = ((b >> 3) * 64 + lane) * 8 + (b & 7);
-            const int cnt = lanes_le(ts.orel, pr);
-            const int32_t sr = __shfl(ts.orel, cnt > 0 ? cnt - 1 : 0);
-            if (bits) {
-                bits &= bits - 1;
-                const int64_t k = min(max(ts.k0 + cnt - 1, (int64_t)0), a.nstr - 1);
-                // (a string's start is needed only when the lane reaches it
-                // first: its lane's offset, or, for the string that began
-                // before the tile, read from memory)
-                const int64_t start = (OP == kOpIs || k == cur_k) ? 0 : cnt > 0 ? tl + sr : off[k] + shift;
-                charge(tl + pr, k, start);
+                    for (int r = 0; r < R; ++r)
+                        bad = bad || groups_in(M[r], r, g0 + 1, g1 - 1) != 0ull;
+                }
+                if (bad)
+                    __hip_atomic_store(a.results + k, (uint8_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            } else {
+                constexpr int kNone = 0x7FFFFFFF;
+                uint32_t cnt = (uint32_t)__popcll(f0) + (uint32_t)cs + (uint32_t)ce;
+                int first = cs ? ul : f0 ? g0 * 8 + (__builtin_ctzll(f0) >> 3) : kNone;
+                if (g1 - g0 >= 2) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        uint64_t m = groups_in(M[r], r, g0 + 1, g1 - 1);
+                        while (m) {
+                            const int l = __builtin_ctzll(m);
+                            m &= m - 1ull;
+                            const uint4 W = w4[l];
+                            const uint64_t b = ((uint64_t)W.y << 32 | W.x) & (kUnits << (7 - r));
+                            cnt += (uint32_t)__popcll(b);
+                            if (first == kNone)
+                                first = (64 * r + l) * 8 + (__builtin_ctzll(b) >> 3);
+                        }
+                    }
+                }
+                cnt += (uint32_t)__popcll(f1);
+                if (first == kNone && f1)
+                    first = g1 * 8 + (__builtin_ctzll(f1) >> 3);
+                if (first == kNone && ce)
+                    first = uh - 1;
+                if (cnt) {
+                    const int64_t start = arl >= 0 ? tl + arl : ac_abs != INT64_MIN ? ac_abs : off[k] + shift;
+                    const uint64_t rel = (uint64_t)(tl + first - start);
+                    if (arl >= 0 && orl <= T) {  // the whole string is in this tile
+                        a.first[k] = (int64_t)rel;
+                        a.count[k] = (int64_t)cnt;
+                    } else {
+                        atomicMin(reinterpret_cast<unsigned long long *>(a.first + k), (unsigned long long)rel);
+                        atomicAdd(reinterpret_cast<unsigned long long *>(a.count + k), (unsigned long long)cnt);
+                    }
+                }
             }
         }
-    } else {
-        while (bits) {
-            const int b = __builtin_ctzll(bits);
-            bits &= bits - 1;
-            const int64_t p = tl + ((b >> 3) * 64 + lane) * 8 + (b & 7);
-            const int64_t k = string_of(off, shift, ts.kc, ts.knext, p, a.nstr);
-            charge(p, k, (OP == kOpIs || k == cur_k) ? 0 : off[k] + shift);
+        if (o63 >= th) {
+            const int c = __popcll(__ballot(o < th));
+            return c > 0 ? lane_value(o, c - 1) : ac >= 0 ? tl + ac : ac_abs;
         }
+        ac = __builtin_amdgcn_readlane(orl, 63);
+        ac_abs = o63;
+        kb += 64;
+        const int64_t o0 = lane_value(o, 0);
+        if (o0 == o63)  // 64 equal offsets: skip the rest of the run of empty strings
+            kb = lower_bound_wave(off, kb, a.nstr + 1, o0 - shift + 1, lane);
+        const int64_t idx = kb + lane;
+        o = idx <= a.nstr ? off[idx] + shift : INT64_MAX;
     }
-    flush();
 }
 
 // ------------------------------------------------------------- the kernel
@@ -450,7 +473,11 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
     constexpr int64_t T = kRowUnits * R;
     constexpr int kWords = 16 * R;
     constexpr bool kFlatLocate = (OP == kOpLocate && !BATCH);
-    __shared__ uint32_t s_bm[BATCH ? kMaxWgWaves * kWords : 1];
+    // check and locate keep no start bitmap; their tiles with several strings
+    // leave mismatch and pair bits here for span_strings
+    constexpr bool kSpans = BATCH && (OP == kOpIs || OP == kOpLocate);
+    __shared__ uint32_t s_bm[(BATCH && !kSpans) ? kMaxWgWaves * kWords : 1];
+    __shared__ uint4 s_w4[kSpans ? kMaxWgWaves * 64 : 1];
     // OP_LOCATE: per-workgroup totals, published by the last wave (batch:
     // for the one string s_loc_k that the first reporting wave names)
     __shared__ unsigned long long s_loc_first, s_loc_k, s_loc_total;
@@ -493,7 +520,10 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
     if (tb >= te && !loc_wg)
         return;  // (such locate waves without tiles still report to their workgroup)
 
-    uint32_t *bm = BATCH ? s_bm + wslot * kWords : nullptr;
+    uint32_t *bm = (BATCH && !kSpans) ? s_bm + wslot * kWords : nullptr;
+    uint4 *w4 = kSpans ? s_w4 + wslot * 64 : nullptr;
+    int64_t o_first = 0;                     // span_strings: the tile's first 64 offsets
+    int64_t span_k = -1, span_start = INT64_MIN;  // start of string span_k, if known
     bool bm_dirty = true;  // LDS starts with arbitrary contents
     // batch isWellFormed: string whose last tile this wave read was whole
     // inside it and clean (-1 if none)
@@ -559,7 +589,7 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
         }
         const bool interior = tl >= lo && th <= hi;
         u32x4 v[R];
-        TileStarts ts{0, 0, 0, 0, 0, false, false, false, false};
+        TileStarts ts{0, 0, 0, 0, false, false, false};
 
         // Batch isWellFormed of few (long) strings checks first whether the
         // whole tile lies in a string already known to be ill-formed; then
@@ -581,11 +611,11 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
                         t = tn - 1;
                     continue;
                 }
-                ts = TileStarts{cursor - 1, cursor, cursor, nxt, (int32_t)T, true, nxt == th, false, false};
+                ts = TileStarts{cursor - 1, cursor, cursor, nxt, nxt == th, false, false};
             } else {
                 if (cursor < 0)
                     cursor = lower_bound_wave(off, 0, a.nstr + 1, tl - shift, lane);
-                ts = scan_starts<R>(off, a.nstr, shift, cursor, tl, th, bm, lane, bm_dirty);
+                ts = scan_starts<R, !kSpans>(off, a.nstr, shift, cursor, tl, th, bm, lane, bm_dirty, &o_first);
                 cursor = ts.knext;
                 nxt = ts.onext;
                 if (!ts.inner && ts.kc >= 0 && ts.kc < a.nstr &&
@@ -620,7 +650,7 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
         if (BATCH && !skip_first) {
             if (cursor < 0)
                 cursor = lower_bound_wave(off, 0, a.nstr + 1, tl - shift, lane);
-            ts = scan_starts<R>(off, a.nstr, shift, cursor, tl, th, bm, lane, bm_dirty);
+            ts = scan_starts<R, !kSpans>(off, a.nstr, shift, cursor, tl, th, bm, lane, bm_dirty, &o_first);
             cursor = ts.knext;
         }
         // batch locate: does the whole tile lie inside one string?
@@ -633,14 +663,122 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
             }
         }
 
+        if constexpr (kSpans) {
+            // Check and locate: every row's flags in one set of words, row r
+            // at bit 7 - r of each byte (the classification puts a flag at
+            // bit 7), so the mismatches and pairs of all rows come from one
+            // pass of the same arithmetic. Computed as in one string; string
+            // starts inside the tile are handled by span_planes.
+            uint32_t HA = 0, HB = 0, LA = 0, LB = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                uint32_t hA, lA, hB, lB;
+                flags4(high_bytes(v[r].x, v[r].y), hA, lA);
+                flags4(high_bytes(v[r].z, v[r].w), hB, lB);
+                HA |= hA >> r;
+                LA |= lA >> r;
+                HB |= hB >> r;
+                LB |= lB >> r;
+            }
+            // Neighbours of all rows at once: the previous lane's unit-7 high
+            // flags and the next lane's unit-0 low flags (DPP wave shifts by
+            // one lane). Lane 0 takes lane 63's flags one row up, lane 63
+            // lane 0's one row down; the tile's ends take a unit of context,
+            // cut by a string start at tl or th.
+            const uint32_t h7 = HB >> 24, l0 = LA & 0xFFu;  // bits 7 - r of byte 0
+            const uint32_t h7_63 = __builtin_amdgcn_readlane(h7, 63), l0_0 = __builtin_amdgcn_readlane(l0, 0);
+            uint32_t cin = 0, cnx = 0;
+            if ((l0_0 & 0x80u) && tl - 1 >= lo && !ts.at_tl)
+                cin = is_high_unit(in[tl - 1]) ? 0x80u : 0u;
+            if ((h7_63 & (0x80u >> (R - 1))) && th < hi && !ts.next)
+                cnx = is_low_unit(in[th]) ? (0x80u >> (R - 1)) : 0u;
+            uint32_t hp = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)h7, 0x138, 0xF, 0xF, true);  // wave_shr:1
+            uint32_t ln = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)l0, 0x130, 0xF, 0xF, true);  // wave_shl:1
+            if (lane == 0)
+                hp = ((h7_63 >> 1) & (0xFFu << (8 - R))) | cin;
+            if (lane == 63)
+                ln = ((l0_0 << 1) & 0xFFu) | cnx;
+            const uint32_t psA = (HA << 8) | hp, psB = (HB << 8) | (HA >> 24);  // predecessor is high
+            const uint32_t nsA = (LA >> 8) | (LB << 24), nsB = (LB >> 8) | (ln << 24);  // successor is low
+            const uint32_t badA = (HA & ~nsA) | (LA & ~psA), badB = (HB & ~nsB) | (LB & ~psB);
+            const uint32_t anyb = badA | badB;
+            if (single) {
+                const uint64_t wb = __ballot(anyb != 0u);
+                if constexpr (OP == kOpIs) {
+                    // The whole tile is string kc: one store settles it. The
+                    // clearing is published device-wide, for the skip test
+                    // of the string's tiles not yet read, only when this wave
+                    // found the string's previous tile clean: its errors are
+                    // then sparse and few waves publish. Where they are dense
+                    // every wave covering the string finds one in its first
+                    // tile, and their coherent stores would queue (200 long
+                    // strings with dense errors past their heads: 128 us when
+                    // every finder published, 78 us under this rule; one
+                    // error late in each: 270 us when none published, 208 us
+                    // under it). Other clearings go through this XCD's
+                    // cache, which the kernel's end writes back.
+                    if (wb && lane == 0) {
+                        if (skip_first && clean_k == ts.kc) {
+                            if (__hip_atomic_load(a.results + ts.kc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+                                __hip_atomic_store(a.results + ts.kc, (uint8_t)0, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                        } else {
+                            __hip_atomic_store(a.results + ts.kc, (uint8_t)0, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
+                    }
+                    clean_k = wb ? -1 : ts.kc;
+                } else if (wb) {
+                    loc_count += (uint32_t)(__popc(badA) + __popc(badB));
+                    if (loc_first == ~0ull) {
+                        int r0 = 0;
+                        uint64_t m0 = 0;
+#pragma unroll
+                        for (int r = R - 1; r >= 0; --r) {
+                            const uint64_t m = __ballot(anyb & (0x80808080u >> r));
+                            if (m) {
+                                r0 = r;
+                                m0 = m;
+                            }
+                        }
+                        const int fl = __builtin_ctzll(m0);
+                        const uint64_t fb = ((uint64_t)(uint32_t)__shfl((int)badB, fl) << 32) |
+                                            (uint32_t)__shfl((int)badA, fl);
+                        const int jf = __builtin_ctzll(fb & (0x0101010101010101ull << (7 - r0))) >> 3;
+                        loc_first = (uint64_t)(tl + ((int64_t)r0 * 64 + fl) * 8 + jf - (off[loc_k] + shift));
+                    }
+                }
+            } else {
+                if constexpr (OP == kOpIs)
+                    clean_k = -1;
+                const uint32_t prA = LA & psA, prB = LB & psB;
+                uint64_t M[R];
+                uint64_t any = 0ull;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    M[r] = __ballot(anyb & (0x80808080u >> r));
+                    any |= M[r];
+                }
+                any |= __ballot((prA | prB) != 0u);
+                const int64_t sp = (span_k >= 0 && span_k == ts.k0 - 1) ? span_start : INT64_MIN;
+                if (any) {
+                    w4[lane] = (uint4){badA, badB, prA, prB};
+                    wave_lds_sync();
+                    span_start = span_planes<OP, R>(a, off, shift, ts.k0, o_first, tl, th, lane, w4, M, sp);
+                } else {
+                    span_start = INT64_MIN;
+                }
+                span_k = ts.knext - 1;
+            }
+            continue;
+        }
+
         // Phase 1: classify every row and ballot the two flags that
         // neighbouring lanes need: "my unit 7 is high" and "my unit 0 is a
         // low that may pair backwards" (not a string start). (Keeping the
         // flags live into phase 2 costs occupancy in the batch kernel but
         // measured faster than classifying again there.)
         uint32_t hA_[R], hB_[R], lA_[R], lB_[R], sbits[R];
-        uint64_t bad_bits = 0;  // batch check / locate: mismatches awaiting their string
-        bool tile_bad = false;  // batch check, whole-tile string: a mismatch was found
         uint64_t hl[R], lf[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -653,10 +791,11 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
 
         // one unit of context at each tile end, read only when it matters
         uint64_t carry_in = 0, carry_nx = 0;
-        if ((lf[0] & 1ull) && tl - 1 >= lo)
+        if ((lf[0] & 1ull) && tl - 1 >= lo && !(kSpans && ts.at_tl))
             carry_in = is_high_unit(in[tl - 1]) ? 1ull : 0ull;
         if ((hl[R - 1] >> 63) && th < hi && !(BATCH && ts.next))
             carry_nx = is_low_unit(in[th]) ? 1ull : 0ull;
+
 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -712,65 +851,18 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
                         }
                         return;
                     }
-                } else if (single) {
-                    // The whole tile is string kc: one store settles it, and
-                    // the tile's remaining rows have nothing left to decide.
-                    // The clearing is published device-wide, for the skip
-                    // test of the string's tiles not yet read, only when this
-                    // wave found the string's previous tile clean: its errors
-                    // are then sparse and few waves publish. Where they are
-                    // dense every wave covering the string finds one in its
-                    // first tile, and their coherent stores would queue. On
-                    // 200 long strings with dense errors past their heads
-                    // the check took 128 us when every finder published and
-                    // 78 us under this rule; with one error late in each,
-                    // 270 us when none published and 208 us under it. Other
-                    // clearings go through this XCD's cache, which the
-                    // kernel's end writes back.
-                    if (wave_bad) {
-                        tile_bad = true;
-                        if (lane == 0) {
-                            if (skip_first && clean_k == ts.kc) {
-                                if (__hip_atomic_load(a.results + ts.kc, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT) != 0)
-                                    __hip_atomic_store(a.results + ts.kc, (uint8_t)0, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-                            } else {
-                                __hip_atomic_store(a.results + ts.kc, (uint8_t)0, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-                            }
-                        }
-                        break;
-                    }
-                } else {
-                    bad_bits |= (uint64_t)pack8(badA, badB) << (8 * r);
                 }
-            } else {  // kOpLocate
-                if (!BATCH || single) {
-                    if (wave_bad) {
-                        loc_count += (uint32_t)__popcll(bad64);
-                        if (loc_first == ~0ull) {
-                            const int fl = __builtin_ctzll(wave_bad);
-                            const int j = lane_bad ? (__builtin_ctzll(bad64) >> 3) : 0;
-                            const int jf = __shfl(j, fl);
-                            const int64_t base = BATCH ? off[loc_k] + shift : lo;
-                            loc_first = (uint64_t)(tl + ((int64_t)r * 64 + fl) * 8 + jf - base);
-                        }
+            } else {  // kOpLocate, one buffer
+                if (wave_bad) {
+                    loc_count += (uint32_t)__popcll(bad64);
+                    if (loc_first == ~0ull) {
+                        const int fl = __builtin_ctzll(wave_bad);
+                        const int j = lane_bad ? (__builtin_ctzll(bad64) >> 3) : 0;
+                        const int jf = __shfl(j, fl);
+                        loc_first = (uint64_t)(tl + ((int64_t)r * 64 + fl) * 8 + jf - lo);
                     }
-                } else {
-                    bad_bits |= (uint64_t)pack8(badA, badB) << (8 * r);
                 }
             }
-        }
-
-        // Batch check and locate, tiles holding several strings: find the
-        // string of each mismatched unit, after the rows (their registers
-        // are free by now). Bit 8r + j of bad_bits is unit j of the lane's
-        // group in row r, so a lane meets its units in increasing order.
-        clean_k = (single && !tile_bad) ? ts.kc : -1;
-        if constexpr (BATCH && (OP == kOpIs || OP == kOpLocate)) {
-            if (!single && __ballot(bad_bits != 0ull))
-                resolve_strings<OP>(a, off, shift, ts, tl, lane, bad_bits);
         }
     }
 
