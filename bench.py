@@ -463,6 +463,25 @@ def profile_batches(torch, wf, W, reps=5):
     torch.cuda.synchronize()
 
 
+def profile_flat(torch, wf, d_in, d_out, reps=2):
+    """Short run for rocprofv3 over the one-buffer kernels other than the
+    out-of-place repair: for each of the five 268,435,456-unit variants in
+    order, `reps` times: restore a scratch copy of the input (a torch copy,
+    untimed by the summaries), repair it in place, then check the input;
+    finally one copy-kernel launch over one buffer (the counters'
+    calibration)."""
+    scratch = d_out[0]
+    res = torch.empty(1, dtype=torch.int32, device="cuda")
+    for x in d_in:
+        for _ in range(reps):
+            scratch.copy_(x)
+            wf.utf16_to_well_formed_inplace(scratch)
+            wf.utf16_is_well_formed(x, res)
+        torch.cuda.synchronize()
+    wf.utf16wf_copy_units(d_in[0], d_out[1])
+    torch.cuda.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -478,6 +497,9 @@ def main():
                     help="short run for rocprofv3: the steps plus one copy-kernel launch, no extras")
     ap.add_argument("--profile-batches", action="store_true",
                     help="run for rocprofv3 over the batch workloads only (no JSON line)")
+    ap.add_argument("--profile-flat", action="store_true",
+                    help="run for rocprofv3: in-place repair and isWellFormed over the five single-buffer "
+                         "variants, then one copy-kernel launch (no JSON line)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -505,6 +527,9 @@ def main():
     d_in = [torch.from_numpy(s.view(np.int16)).cuda() for s in host_inputs]
     d_out = [torch.empty_like(x) for x in d_in]
     torch.cuda.synchronize()
+    if args.profile_flat:
+        profile_flat(torch, wf, d_in, d_out)
+        return
 
     launches = Timer(torch, stream)
 

@@ -74,15 +74,18 @@ __device__ __forceinline__ uint32_t unit_of(u32x4 v, int j) {
     return (j & 1) ? (d >> 16) : (d & 0xFFFFu);
 }
 
-// Units u0..u0+7 with those outside [lo, hi) read as 0 (a non-surrogate).
+// Units u0..u0+7 with those outside [lo, hi) read as 0 (a non-surrogate);
+// needs hi > lo. Every load reads a unit inside [lo, hi) (its index clamped
+// there) and the select comes after, so the eight loads carry no branch and
+// issue together under one wait.
 __device__ __forceinline__ u32x4 ld_partial(const uint16_t *in, int64_t u0, int64_t lo, int64_t hi) {
     uint32_t w[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
         const int64_t a = u0 + 2 * d, b = a + 1;
-        const uint32_t x = (a >= lo && a < hi) ? (uint32_t)in[a] : 0u;
-        const uint32_t y = (b >= lo && b < hi) ? (uint32_t)in[b] : 0u;
-        w[d] = x | (y << 16);
+        const uint32_t x = in[min(max(a, lo), hi - 1)];
+        const uint32_t y = in[min(max(b, lo), hi - 1)];
+        w[d] = ((a >= lo && a < hi) ? x : 0u) | ((b >= lo && b < hi) ? y << 16 : 0u);
     }
     return (u32x4){w[0], w[1], w[2], w[3]};
 }
@@ -97,6 +100,30 @@ __device__ __forceinline__ void st_partial(uint16_t *out, int64_t u0, int64_t lo
         if (u >= lo && u < hi && ((sel >> (8 * j + 7)) & 1))
             out[u] = (uint16_t)unit_of(v, j);
     }
+}
+
+// One row of a tile that crosses lo or hi (hi > lo): the row starting at
+// unit r0 (the same for the whole wave) is loaded with 16-byte vectors when
+// it lies inside [lo, hi), not at all when it lies outside, and unit by unit
+// only when it straddles an end. The tests are on wave-uniform values, so
+// they are scalar branches. in + r0 is 16-byte aligned.
+template <bool NT>
+__device__ __forceinline__ u32x4 ld_row(const uint16_t *in, int64_t r0, int lane, int64_t lo, int64_t hi) {
+    const int64_t u0 = r0 + (int64_t)lane * 8;
+    if (r0 >= lo && r0 + kRowUnits <= hi)
+        return ld16<NT>(in + u0);
+    if (r0 + kRowUnits <= lo || r0 >= hi)
+        return (u32x4){0u, 0u, 0u, 0u};
+    return ld_partial(in, u0, lo, hi);
+}
+
+template <bool NT>
+__device__ __forceinline__ void st_row(uint16_t *out, int64_t r0, int lane, int64_t lo, int64_t hi, u32x4 v) {
+    const int64_t u0 = r0 + (int64_t)lane * 8;
+    if (r0 >= lo && r0 + kRowUnits <= hi)
+        st16<NT>(out + u0, v);
+    else if (r0 + kRowUnits > lo && r0 < hi)
+        st_partial(out, u0, lo, hi, v, 0x8080808080808080ull);
 }
 
 // ---------------------------------------------------------- classification
@@ -497,7 +524,9 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
     }
 
     const int lane = __lane_id();
-    const int wslot = threadIdx.x >> 6;
+    // the wave's slot in its workgroup, known to the compiler as wave-uniform,
+    // so tile indices, loop bounds and tile-edge tests live in scalar registers
+    const int wslot = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t wg_waves = blockDim.x >> 6;
     const int64_t nwaves = (int64_t)gridDim.x * wg_waves;
     const int64_t wave = (int64_t)blockIdx.x * wg_waves + wslot;
@@ -637,7 +666,7 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
             if (interior)
                 v[r] = ld16<NT>(in + u0);
             else
-                v[r] = ld_partial(in, u0, lo, hi);
+                v[r] = ld_row<NT>(in, tl + (int64_t)r * kRowUnits, lane, lo, hi);
         }
         if constexpr (OP == kOpIs && !BATCH)
             poll = __hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -821,7 +850,7 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
                 } else if (interior) {
                     st16<NT>(out + u0, o);
                 } else {
-                    st_partial(out, u0, lo, hi, o, 0x8080808080808080ull);
+                    st_row<NT>(out, tl + (int64_t)r * kRowUnits, lane, lo, hi, o);
                 }
             } else if constexpr (OP == kOpToInplace) {
                 // Inside the buffer, the eight lanes of a 128-byte line store
@@ -942,7 +971,7 @@ constexpr int64_t kHeadMinUnits = 8192;
 __global__ void __launch_bounds__(256) head_check_kernel(const uint16_t *in, const int64_t *off, int64_t nstr,
                                                          int64_t shift, uint8_t *results) {
     const int lane = __lane_id();
-    const int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (k >= nstr)
         return;
     const int64_t s0 = off[k] + shift, s1 = off[k + 1] + shift;
@@ -975,7 +1004,7 @@ __global__ void __launch_bounds__(1024) wf_multi_kernel(MultiArgs a) {
     const int lane = __lane_id();
     const int64_t wg_waves = blockDim.x >> 6;
     const int64_t nwaves = (int64_t)gridDim.x * wg_waves;
-    const int64_t wave = (int64_t)blockIdx.x * wg_waves + (threadIdx.x >> 6);
+    const int64_t wave = (int64_t)blockIdx.x * wg_waves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t per = (a.ntiles + nwaves - 1) / nwaves;
     const int64_t vb = wave * per, ve = min(vb + per, a.ntiles);
     if (vb >= ve)
@@ -1005,7 +1034,7 @@ __global__ void __launch_bounds__(1024) wf_multi_kernel(MultiArgs a) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t u0 = tl + ((int64_t)r * 64 + lane) * 8;
-            v[r] = interior ? ld16<NT>(in + u0) : ld_partial(in, u0, lo, hi);
+            v[r] = interior ? ld16<NT>(in + u0) : ld_row<NT>(in, tl + (int64_t)r * kRowUnits, lane, lo, hi);
         }
         if constexpr (OP == kOpIs) {
             poll = __hip_atomic_load(a.results + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1046,7 +1075,7 @@ __global__ void __launch_bounds__(1024) wf_multi_kernel(MultiArgs a) {
                 } else if (interior) {
                     st16<NT>(out + u0, o);
                 } else {
-                    st_partial(out, u0, lo, hi, o, 0x8080808080808080ull);
+                    st_row<NT>(out, tl + (int64_t)r * kRowUnits, lane, lo, hi, o);
                 }
             } else {
                 if (wave_bad) {
@@ -1080,7 +1109,7 @@ __global__ void __launch_bounds__(1024) copy_kernel(const uint16_t *in, uint16_t
     const int lane = __lane_id();
     const int64_t wg_waves = blockDim.x >> 6;
     const int64_t nwaves = (int64_t)gridDim.x * wg_waves;
-    const int64_t wave = (int64_t)blockIdx.x * wg_waves + (threadIdx.x >> 6);
+    const int64_t wave = (int64_t)blockIdx.x * wg_waves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (hi <= lo)
         return;
     const int64_t t0 = lo / T, t1 = (hi + T - 1) / T;
@@ -1094,7 +1123,7 @@ __global__ void __launch_bounds__(1024) copy_kernel(const uint16_t *in, uint16_t
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t u0 = tl + ((int64_t)r * 64 + lane) * 8;
-            v[r] = interior ? ld16<NT>(in + u0) : ld_partial(in, u0, lo, hi);
+            v[r] = interior ? ld16<NT>(in + u0) : ld_row<NT>(in, tl + (int64_t)r * kRowUnits, lane, lo, hi);
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -1102,7 +1131,7 @@ __global__ void __launch_bounds__(1024) copy_kernel(const uint16_t *in, uint16_t
             if (interior)
                 st16<NT>(out + u0, v[r]);
             else
-                st_partial(out, u0, lo, hi, v[r], 0x8080808080808080ull);
+                st_row<NT>(out, tl + (int64_t)r * kRowUnits, lane, lo, hi, v[r]);
         }
     }
 }

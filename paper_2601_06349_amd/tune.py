@@ -144,7 +144,9 @@ def _sweep(wf, run, op, batch, size_class, calls, reps, quick, finalists=5, targ
     return best[2], best[1], default_ms
 
 
-def tune(quick=False, flat_classes=None, out=None, log=print):
+def tune(quick=False, flat_classes=None, out=None, log=print, batch_only=False):
+    """Sweep launch shapes and write the cache. batch_only keeps the flat
+    entries of the existing cache and re-tunes the batch keys alone."""
     import torch
 
     import paper_2601_06349_amd as wf
@@ -152,7 +154,12 @@ def tune(quick=False, flat_classes=None, out=None, log=print):
 
     run = _timer(torch)
     entries = []
-    flat_classes = flat_classes or (list(range(10, 29, 2)) if quick else list(range(10, 29)))
+    if batch_only:
+        with open(out or cache_path()) as f:
+            entries = [e for e in json.load(f)["entries"] if e["batch"] == 0]
+        flat_classes = []
+    if flat_classes is None:
+        flat_classes = list(range(10, 29, 2)) if quick else list(range(10, 29))
     names = {wf.OP_IS: "is", wf.OP_TO: "to", wf.OP_TO_INPLACE: "to_inplace", wf.OP_LOCATE: "locate"}
     t_start = time.time()
     # Representative inputs: the five kinds of content of the single-buffer
@@ -160,7 +167,7 @@ def tune(quick=False, flat_classes=None, out=None, log=print):
     # and 1e-2, all units surrogates), drawn with other seeds, each copy
     # written to its own output. A shape is scored on the sum over them, so
     # it is tuned neither to one kind of content nor to a re-written buffer.
-    top = 1 << max(flat_classes)
+    top = 1 << max(flat_classes, default=10)
     kinds = W.SINGLE_VARIANTS
     d_in = {v: torch.from_numpy(W.single_buffer(v, n=top, seed=4242 + i).view(np.int16)).cuda()
             for i, v in enumerate(kinds)}
@@ -194,15 +201,18 @@ def tune(quick=False, flat_classes=None, out=None, log=print):
             log(f"flat {names[op]:10s} 2^{c:2d}: tuned {ms * 1e3:9.1f} us  default {dms * 1e3:9.1f} us  {params}")
     del d_in, d_outs, d_tmp
 
-    # batches: the Zipf(1.1) 4096-string workload (1.58G units) and the
-    # 1,000,000 log-normal strings (98.6M units). Unknown sizes (no hint,
-    # class 40) are tuned on both, weighted alike; hinted calls on the one of
+    # batches: the Zipf(1.1) 4096-string workload (1.58G units), the
+    # 1,000,000 log-normal strings (98.6M units) and 262,144 JavaScript-shape
+    # strings of 1024 units (268M units). Unknown sizes (no hint, class 40)
+    # are tuned on the first two, weighted alike; hinted calls on the one of
     # their size (class 30: Zipf, the nearest tuned class for large batches;
-    # class 26: the log-normal batch, for smaller ones).
+    # class 28: the 1024-unit strings; class 26: the log-normal batch, for
+    # smaller ones).
     zb, zoff, _ = W.zipf_batch()
     rb, roff = W.ragged_batch()
+    jb, joff = W.js_batch()
     dev = {}
-    for label, buf, off in (("zipf_4096", zb, zoff), ("ragged_1m", rb, roff)):
+    for label, buf, off in (("zipf_4096", zb, zoff), ("ragged_1m", rb, roff), ("js_262144", jb, joff)):
         t_in = torch.from_numpy(buf.view(np.int16)).cuda()
         b = off.size - 1
         dev[label] = {"in": t_in, "off": torch.from_numpy(off).cuda(), "out": torch.empty_like(t_in),
@@ -223,6 +233,7 @@ def tune(quick=False, flat_classes=None, out=None, log=print):
 
     keys = [("zipf_4096", int(np.floor(np.log2(dev["zipf_4096"]["units"]))), [("zipf_4096", True)]),
             ("ragged_1m", int(np.floor(np.log2(dev["ragged_1m"]["units"]))), [("ragged_1m", True)]),
+            ("js_262144", int(np.floor(np.log2(dev["js_262144"]["units"]))), [("js_262144", True)]),
             ("zipf_4096 + ragged_1m, no hint", 40, [("zipf_4096", False), ("ragged_1m", False)])]
     best_ms = {}  # (workload, op) -> its own tuned time, the targets of the no-hint class
     for label, cls, which in keys:
@@ -254,8 +265,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="keep the cache's flat entries; re-tune the batch keys")
     args = ap.parse_args()
-    tune(quick=args.quick, out=args.out, log=lambda m: print(m, flush=True))
+    tune(quick=args.quick, out=args.out, log=lambda m: print(m, flush=True), batch_only=args.batch_only)
     return 0
 
 
