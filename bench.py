@@ -437,9 +437,10 @@ def host_resident(torch, wf, host_input):
 def profile_batches(torch, wf, W, reps=5):
     """Short run for rocprofv3 over the batch workloads, in a fixed order:
     for the 1,000,000-string batch and then the 4096-string Zipf batch, each
-    with its size hint, `reps` calls each of the out-of-place repair, the
-    check and the locate; then one copy-kernel launch over 268,435,456 units
-    (the counters' calibration)."""
+    with its size hint, 1 + `reps` calls each of the out-of-place repair, the
+    check and the locate (the first of each a warm-up, as the benchmark's
+    timed calls follow warm-up calls); then one copy-kernel launch over
+    268,435,456 units (the counters' calibration)."""
     for label, (buf, off), hinted in (("ragged 1M", W.ragged_batch(), True),
                                       ("zipf 4096", W.zipf_batch()[:2], True)):
         log(f"profile: {label}")
@@ -453,7 +454,7 @@ def profile_batches(torch, wf, W, reps=5):
         hint = int(off[-1]) if hinted else 0
         for op, kw in ((wf.OP_TO, {"out": t_out}), (wf.OP_IS, {"results": res}),
                        (wf.OP_LOCATE, {"first": first, "count": count})):
-            for _ in range(reps):
+            for _ in range(1 + reps):
                 wf.utf16wf_batch(op, t_in, t_off, units_hint=hint, **kw)
             torch.cuda.synchronize()
         del t_in, t_out

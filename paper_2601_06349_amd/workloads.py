@@ -41,6 +41,7 @@ SEEDS = {
     "single_mix1e-2": 1104,
     "single_allsur": 1105,
     "ragged_1m": 1201,
+    "small_batch": 1204,
     "zipf_4096": 1301,
     "serve": 1401,
     "paper_1m": 1501,
@@ -161,13 +162,13 @@ def offsets_from_lengths(lengths, base: int = 0) -> np.ndarray:
     return off
 
 
-def ragged_batch(b=1_000_000, seed=SEEDS["ragged_1m"], edge_p=0.05, r=1e-3):
-    """(buf, offsets): b strings with log-normal lengths (median 32, sigma 1.5,
-    clamped to 1..65,536) cut from one mix(r) stream; each string's last unit
-    is forced to a lone high and its first unit to a lone low, independently
-    with probability ``edge_p`` each."""
+def ragged_batch(b=1_000_000, seed=SEEDS["ragged_1m"], edge_p=0.05, r=1e-3, median=32.0):
+    """(buf, offsets): b strings with log-normal lengths (median ``median``,
+    sigma 1.5, clamped to 1..65,536) cut from one mix(r) stream; each string's
+    last unit is forced to a lone high and its first unit to a lone low,
+    independently with probability ``edge_p`` each."""
     rng = _rng(seed)
-    lens = lognormal_lengths(b, rng)
+    lens = lognormal_lengths(b, rng, median=median)
     off = offsets_from_lengths(lens)
     buf = mix(int(off[-1]), r, rng)
     ends = off[1:][rng.random(b) < edge_p] - 1
@@ -175,6 +176,12 @@ def ragged_batch(b=1_000_000, seed=SEEDS["ragged_1m"], edge_p=0.05, r=1e-3):
     starts = off[:-1][rng.random(b) < edge_p]
     buf[starts] = (0xDC00 + rng.integers(0, 1024, size=starts.size)).astype(np.uint16)
     return buf, off
+
+
+def small_batch():
+    """A serving-size batch: 32 strings of the log-normal batch's shape at
+    median 1024 units (about 10^5 units in all)."""
+    return ragged_batch(b=32, seed=SEEDS["small_batch"], median=1024.0)
 
 
 def zipf_lengths(b: int, rng, s=1.1, max_len=1 << 24) -> np.ndarray:
