@@ -202,12 +202,17 @@ int utf16wf_batch_plan_destroy(void *plan);
 /* Launch parameters of the kernels. rows: 16-byte loads in flight per lane
  * per tile (1, 2, 4 or 8; a tile is rows * 512 units per wave). wg_waves:
  * waves per workgroup (1..16). grid_per_cu: workgroups per compute unit of a
- * full persistent grid (1..64). nontemporal: 0/1, streaming cache hints. */
+ * full persistent grid (1..64). nontemporal: 0/1, streaming cache hints.
+ * store_lines: 0/1, the in-place repair's store mode (Sec. 3.2 writes only
+ * where something changed): 1 writes every 128-byte line that holds a change
+ * whole (the line's unchanged units written back as read), 0 writes only the
+ * 16-byte vectors that changed; the other operations ignore it (default 1). */
 typedef struct {
     int32_t rows;
     int32_t wg_waves;
     int32_t grid_per_cu;
     int32_t nontemporal;
+    int32_t store_lines;
 } utf16wf_params;
 
 /* Set the parameters used for (op, batch 0/1, size class). size_class is

@@ -281,8 +281,8 @@ class BatchPlan:
             pass
 
 
-def set_params(op, batch, size_class, rows, wg_waves, grid_per_cu, nontemporal):
-    p = Params(rows, wg_waves, grid_per_cu, nontemporal)
+def set_params(op, batch, size_class, rows, wg_waves, grid_per_cu, nontemporal, store_lines=1):
+    p = Params(rows, wg_waves, grid_per_cu, nontemporal, store_lines)
     check(lib().utf16wf_set_params(int(op), int(batch), int(size_class), ctypes.byref(p)))
 
 

@@ -40,7 +40,11 @@ class Utf16wfError(RuntimeError):
 
 class Params(ctypes.Structure):
     _fields_ = [("rows", ctypes.c_int32), ("wg_waves", ctypes.c_int32),
-                ("grid_per_cu", ctypes.c_int32), ("nontemporal", ctypes.c_int32)]
+                ("grid_per_cu", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
+                ("store_lines", ctypes.c_int32)]
+
+    def __init__(self, rows=0, wg_waves=0, grid_per_cu=0, nontemporal=0, store_lines=1):
+        super().__init__(rows, wg_waves, grid_per_cu, nontemporal, store_lines)
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

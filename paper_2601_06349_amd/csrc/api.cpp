@@ -88,6 +88,7 @@ utf16wf_params default_params(int op, int batch, int cls) {
     p.wg_waves = 4;
     p.grid_per_cu = 8;
     p.nontemporal = 0;
+    p.store_lines = 1;
     (void)op;
     return p;
 }
@@ -114,7 +115,7 @@ int size_class(int64_t n) {
 bool params_ok(const utf16wf_params &p) {
     const bool rows_ok = p.rows == 1 || p.rows == 2 || p.rows == 4 || p.rows == 8;
     return rows_ok && p.wg_waves >= 1 && p.wg_waves <= 16 && p.grid_per_cu >= 1 && p.grid_per_cu <= 64 &&
-           (p.nontemporal == 0 || p.nontemporal == 1);
+           (p.nontemporal == 0 || p.nontemporal == 1) && (p.store_lines == 0 || p.store_lines == 1);
 }
 
 // The parameters set for n's size class; for a class that has none, those
@@ -140,6 +141,7 @@ LaunchShape make_shape(const utf16wf_params &p, int cus, int64_t units, int64_t 
     s.rows = p.rows;
     s.wg_waves = p.wg_waves;
     s.nontemporal = p.nontemporal;
+    s.store_lines = p.store_lines;
     const int64_t max_waves = (int64_t)p.grid_per_cu * cus * p.wg_waves;
     int64_t waves = max_waves;
     if (units > 0) {
@@ -486,6 +488,7 @@ int strings_call(int op, int n, const uint16_t *const *src, uint16_t *const *dst
     sh.rows = p.rows;
     sh.wg_waves = p.wg_waves;
     sh.nontemporal = p.nontemporal;
+    sh.store_lines = p.store_lines;
     const int64_t waves = std::min<int64_t>(tiles, (int64_t)p.grid_per_cu * cus * p.wg_waves);
     sh.grid = (int)std::max<int64_t>(1, (waves + p.wg_waves - 1) / p.wg_waves);
     hipError_t e;
@@ -508,7 +511,7 @@ struct Plan {
 
 extern "C" {
 
-int utf16wf_abi_version(void) { return 1; }
+int utf16wf_abi_version(void) { return 2; }
 
 const char *utf16wf_last_error(void) { return g_err.c_str(); }
 
@@ -731,8 +734,9 @@ int utf16wf_set_params(int op, int batch, int size_class_, const utf16wf_params 
     if (!p || (batch != 0 && batch != 1) || size_class_ < -1 || size_class_ >= kClasses)
         return fail(UTF16WF_EINVAL, "bad tuning key");
     if (!params_ok(*p))
-        return fail(UTF16WF_EINVAL, "bad parameters (rows %d, wg_waves %d, grid_per_cu %d, nontemporal %d)", p->rows,
-                    p->wg_waves, p->grid_per_cu, p->nontemporal);
+        return fail(UTF16WF_EINVAL,
+                    "bad parameters (rows %d, wg_waves %d, grid_per_cu %d, nontemporal %d, store_lines %d)", p->rows,
+                    p->wg_waves, p->grid_per_cu, p->nontemporal, p->store_lines);
     std::lock_guard<std::mutex> lk(g_param_mu);
     init_params_locked();
     if (size_class_ < 0) {

@@ -14,6 +14,7 @@ struct LaunchShape {
     int wg_waves;     // waves per workgroup, 1..16
     int grid;         // workgroups
     int nontemporal;  // 0/1
+    int store_lines;  // in-place repair: 1 whole 128-byte lines, 0 changed 16-byte vectors
 };
 
 // One launch of the repair/check kernel.

@@ -513,6 +513,11 @@ __device__ __forceinline__ int64_t span_planes(const KernelArgs &a, const int64_
 
 // ------------------------------------------------------------- the kernel
 
+// OP: the operation; BATCH: ragged batch (else one buffer); R: rows per tile;
+// NT: non-temporal loads and stores. SS, out-of-place repair: the output's
+// address phase differs from the input's (stores are realigned); in-place
+// repair: sector stores (only the 16-byte vectors that changed are written,
+// instead of every 128-byte line that holds a change).
 template <int OP, bool BATCH, int R, bool NT, bool SS>
 __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
     constexpr int64_t T = kRowUnits * R;
@@ -885,8 +890,12 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
                 // writes rather than partial ones; unchanged lanes write back
                 // the values they read, which no other wave writes.
                 if (interior) {
-                    if ((wave_bad >> (lane & ~7)) & 0xFFull)
+                    if constexpr (SS) {
+                        if (lane_bad)
+                            st16<NT>(out + u0, repair(v[r], badA, badB));
+                    } else if ((wave_bad >> (lane & ~7)) & 0xFFull) {
                         st16<NT>(out + u0, lane_bad ? repair(v[r], badA, badB) : v[r]);
+                    }
                 } else if (lane_bad) {
                     st_partial(out, u0, lo, hi, repair(v[r], badA, badB), bad64);
                 }
@@ -1279,10 +1288,18 @@ hipError_t fill(T *p, T v, int64_t n, hipStream_t s) {
 template <int OP, bool BATCH, int R, bool NT>
 hipError_t launch_r(const LaunchShape &sh, const KernelArgs &a, hipStream_t s) {
     const dim3 grid((unsigned)sh.grid), block((unsigned)(64 * sh.wg_waves));
-    if (OP == kOpTo && a.scalar_store)
-        hipLaunchKernelGGL((wf_kernel<OP, BATCH, R, NT, true>), grid, block, 0, s, a);
-    else
-        hipLaunchKernelGGL((wf_kernel<OP, BATCH, R, NT, false>), grid, block, 0, s, a);
+    bool alt = false;  // the SS variant: realigned stores, or sector stores in place
+    if constexpr (OP == kOpTo)
+        alt = a.scalar_store != 0;
+    else if constexpr (OP == kOpToInplace)
+        alt = sh.store_lines == 0;
+    if constexpr (OP == kOpTo || OP == kOpToInplace) {
+        if (alt) {
+            hipLaunchKernelGGL((wf_kernel<OP, BATCH, R, NT, true>), grid, block, 0, s, a);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((wf_kernel<OP, BATCH, R, NT, false>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 

@@ -8,7 +8,9 @@ kinds of content of the single-buffer workload, launched in turn, each into
 its own output; for batches of unknown size, over the Zipf and the
 log-normal batch, keeping the shape whose worse slowdown against each
 batch's own tuned time is smallest),
-re-times the best few with more repetitions, and keeps the fastest. The
+re-times the best few with more repetitions — the in-place repair's in both
+store modes (whole 128-byte lines, or only the 16-byte vectors that changed),
+on inputs restored before each call — and keeps the fastest. The
 untuned default is timed beside it and both are written to the cache, so the
 gain is visible. Size classes without an entry use the nearest tuned class.
 
@@ -68,7 +70,7 @@ def apply_cache(path=None):
     for e in data.get("entries", []):
         p = e["params"]
         wf.set_params(e["op"], e["batch"], e["size_class"], p["rows"], p["wg_waves"], p["grid_per_cu"],
-                      p["nontemporal"])
+                      p["nontemporal"], p.get("store_lines", 1))
     return os.path.basename(path)
 
 
@@ -76,16 +78,27 @@ def _timer(torch):
     """run(calls, reps) -> the mean launch time (ms) of each call.
     The calls are interleaved launch by launch, so consecutive launches work
     on different buffers (as in the benchmark) and a large input is never
-    re-read while it may still sit in the last-level cache."""
+    re-read while it may still sit in the last-level cache. A call given as
+    (setup, fn) runs setup untimed before each fn (e.g. restoring the input
+    of an in-place repair)."""
     stream = torch.cuda.current_stream()
 
+    def split(c):
+        return c if isinstance(c, tuple) else (None, c)
+
     def run(calls, reps):
-        for fn in calls:
+        for c in calls:
+            setup, fn = split(c)
+            if setup:
+                setup()
             fn()
         torch.cuda.synchronize()
         evs = [[] for _ in calls]
         for _ in range(reps):
-            for i, fn in enumerate(calls):
+            for i, c in enumerate(calls):
+                setup, fn = split(c)
+                if setup:
+                    setup()
                 a = torch.cuda.Event(enable_timing=True)
                 b = torch.cuda.Event(enable_timing=True)
                 a.record(stream)
@@ -110,15 +123,16 @@ def shapes(quick=False):
     return list(itertools.product(ROWS, WG_WAVES, GRID_PER_CU, NONTEMPORAL))
 
 
-def _sweep(wf, run, op, batch, size_class, calls, reps, quick, finalists=5, targets=None):
+def _sweep(wf, run, op, batch, size_class, calls, reps, quick, finalists=5, targets=None, store_modes=(1,)):
     """Time every shape for one key over every call in ``calls`` (the same
     operation on different representative inputs), then re-time the best few
-    with three times the repetitions. A shape's score is the sum of its mean
-    launch times over the calls, or, given ``targets`` (a time per call, e.g.
-    each input's own tuned time), the largest ratio of a call's time to its
-    target: the shape whose worst slowdown is smallest. A shape is kept only
-    if its plain sum also beats the default's. Returns (best_params, best_ms,
-    default_ms), times summed over the inputs."""
+    with three times the repetitions, in each of ``store_modes`` (the
+    in-place repair's: 1 whole lines, 0 changed vectors). A shape's score is
+    the sum of its mean launch times over the calls, or, given ``targets`` (a
+    time per call, e.g. each input's own tuned time), the largest ratio of a
+    call's time to its target: the shape whose worst slowdown is smallest. A
+    shape is kept only if its plain sum also beats the default's. Returns
+    (best_params, best_ms, default_ms), times summed over the inputs."""
     wf.reset_params()
     default = wf.get_params(op, batch, 1 << size_class if size_class < 40 else 1 << 40)
     base = run(calls, reps * 3)
@@ -136,10 +150,12 @@ def _sweep(wf, run, op, batch, size_class, calls, reps, quick, finalists=5, targ
     scored.sort()
     best = (score(base), default_ms, default)
     for _, (rows, wg, gpc, nt) in scored[:finalists]:
-        wf.set_params(op, batch, size_class, rows, wg, gpc, nt)
-        times = run(calls, reps * 3)
-        if score(times) < best[0] and sum(times) <= default_ms:
-            best = (score(times), sum(times), {"rows": rows, "wg_waves": wg, "grid_per_cu": gpc, "nontemporal": nt})
+        for sl in store_modes:
+            wf.set_params(op, batch, size_class, rows, wg, gpc, nt, sl)
+            times = run(calls, reps * 3)
+            if score(times) < best[0] and sum(times) <= default_ms:
+                best = (score(times), sum(times),
+                        {"rows": rows, "wg_waves": wg, "grid_per_cu": gpc, "nontemporal": nt, "store_lines": sl})
     wf.reset_params()
     return best[2], best[1], default_ms
 
@@ -180,13 +196,13 @@ def tune(quick=False, flat_classes=None, out=None, log=print, batch_only=False):
         x = {v: d_in[v][:n] for v in kinds}
         ys = [o[:n] for o in d_outs]
         z1, z2 = d_tmp[0][:n], d_tmp[1][:n]
-        z1.copy_(x["mix1e-2"])
         z2.copy_(x["ascii"])
         r32 = res[:1].view(torch.int32)
         calls = {
             wf.OP_TO: [(lambda a=x[v], b=ys[i]: wf.utf16_to_well_formed(a, b)) for i, v in enumerate(kinds)],
-            # in place: after its first call a buffer is clean (the common case)
-            wf.OP_TO_INPLACE: [lambda: wf.utf16_to_well_formed_inplace(z1),
+            # in place: the 1e-2 mix, restored before each call (untimed), and
+            # a clean buffer, which the repair leaves as it is
+            wf.OP_TO_INPLACE: [(lambda: z1.copy_(x["mix1e-2"]), lambda: wf.utf16_to_well_formed_inplace(z1)),
                                lambda: wf.utf16_to_well_formed_inplace(z2)],
             # isWellFormed: full passes over clean inputs (errors end it early)
             wf.OP_IS: [lambda: wf.utf16_is_well_formed(x["mix0"], r32),
@@ -195,7 +211,8 @@ def tune(quick=False, flat_classes=None, out=None, log=print, batch_only=False):
                            lambda: wf.utf16_locate_ill_formed(x["mix0"])],
         }
         for op, cs in calls.items():
-            params, ms, dms = _sweep(wf, run, op, 0, c, cs, reps, quick)
+            modes = (1, 0) if op == wf.OP_TO_INPLACE else (1,)
+            params, ms, dms = _sweep(wf, run, op, 0, c, cs, reps, quick, store_modes=modes)
             entries.append({"op": op, "op_name": names[op], "batch": 0, "size_class": c, "params": params,
                             "tuned_ms": round(ms, 5), "default_ms": round(dms, 5), "inputs": len(cs)})
             log(f"flat {names[op]:10s} 2^{c:2d}: tuned {ms * 1e3:9.1f} us  default {dms * 1e3:9.1f} us  {params}")
@@ -229,7 +246,9 @@ def tune(quick=False, flat_classes=None, out=None, log=print, batch_only=False):
         if op == wf.OP_TO:
             return lambda: wf.utf16wf_batch(op, d["in"], d["off"], out=d["out"], units_hint=hint)
         if op == wf.OP_TO_INPLACE:
-            return lambda: wf.utf16wf_batch(op, d["ip"], d["off"], out=d["ip"], units_hint=hint)
+            # restored before each call (untimed), so every call repairs
+            return (lambda: d["ip"].copy_(d["in"]),
+                    lambda: wf.utf16wf_batch(op, d["ip"], d["off"], out=d["ip"], units_hint=hint))
         if op == wf.OP_LOCATE:
             return lambda: wf.utf16wf_batch(op, d["in"], d["off"], first=d["first"], count=d["count"],
                                             units_hint=hint)
@@ -247,7 +266,8 @@ def tune(quick=False, flat_classes=None, out=None, log=print, batch_only=False):
             targets = [best_ms[(w, op)] for w, _ in which] if cls == 40 else None
             # short calls (the small batch) get more repetitions
             reps_b = 5 if min(dev[w]["units"] for w, _ in which) >= 1 << 24 else 40
-            params, ms, dms = _sweep(wf, run, op, 1, cls, calls, reps_b, quick, targets=targets)
+            modes = (1, 0) if op == wf.OP_TO_INPLACE else (1,)
+            params, ms, dms = _sweep(wf, run, op, 1, cls, calls, reps_b, quick, targets=targets, store_modes=modes)
             if cls != 40:
                 best_ms[(label, op)] = ms
             entries.append({"op": op, "op_name": names[op], "batch": 1, "size_class": cls, "params": params,

@@ -66,7 +66,7 @@ def test_headers_compile_as_c(tmp_path):
 
 
 def test_abi_version(L):
-    assert L.utf16wf_abi_version() == 1
+    assert L.utf16wf_abi_version() == 2
 
 
 def _rc(L, name, *args):
@@ -213,7 +213,13 @@ def test_params_roundtrip(L):
     assert d["rows"] in (1, 2, 4, 8) and 1 <= d["wg_waves"] <= 16
     wf.set_params(wf.OP_TO, 0, 28, rows=8, wg_waves=2, grid_per_cu=3, nontemporal=1)
     assert wf.get_params(wf.OP_TO, 0, (1 << 28) + 5) == {"rows": 8, "wg_waves": 2, "grid_per_cu": 3,
-                                                         "nontemporal": 1}
+                                                         "nontemporal": 1, "store_lines": 1}
+    # the in-place store mode: whole lines by default, changed vectors on request
+    assert wf.get_params(wf.OP_TO_INPLACE, 0, 1 << 28)["store_lines"] == 1
+    wf.set_params(wf.OP_TO_INPLACE, 0, 28, rows=4, wg_waves=4, grid_per_cu=8, nontemporal=0, store_lines=0)
+    assert wf.get_params(wf.OP_TO_INPLACE, 0, 1 << 28)["store_lines"] == 0
+    with pytest.raises(wf.Utf16wfError):
+        wf.set_params(wf.OP_TO_INPLACE, 0, 28, rows=4, wg_waves=4, grid_per_cu=8, nontemporal=0, store_lines=2)
     assert wf.get_params(wf.OP_TO, 0, 1 << 27) == wf.get_params(wf.OP_TO, 0, (1 << 27) + 1)
     # nearest set class: 2^30 units fall back to class 28
     assert wf.get_params(wf.OP_TO, 0, 1 << 30)["rows"] == 8
@@ -253,7 +259,7 @@ def test_tuning_cache_applies(tmp_path, L):
     try:
         assert tune.apply_cache(str(path)) == "cache.json"
         assert wf.get_params(wf.OP_TO, 0, 1 << 20) == {"rows": 2, "wg_waves": 16, "grid_per_cu": 5,
-                                                      "nontemporal": 1}
+                                                      "nontemporal": 1, "store_lines": 1}
         assert wf.get_params(wf.OP_IS, 1, 1 << 40)["grid_per_cu"] == 64
         # classes without an entry take the nearest class that has one
         assert wf.get_params(wf.OP_TO, 0, 1 << 21) == wf.get_params(wf.OP_TO, 0, 1 << 20)
@@ -280,4 +286,5 @@ def test_committed_tuning_cache_is_valid():
             p = e["params"]
             assert e["op"] in (0, 1, 2, 3) and e["batch"] in (0, 1) and 0 <= e["size_class"] <= 40
             assert p["rows"] in (1, 2, 4, 8) and 1 <= p["wg_waves"] <= 16 and 1 <= p["grid_per_cu"] <= 64
+            assert p.get("store_lines", 1) in (0, 1)
             assert e["tuned_ms"] <= e["default_ms"] * 1.0001

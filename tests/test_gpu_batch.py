@@ -26,9 +26,10 @@ def wf():
     wf.reset_params()
 
 
-def _force_rows(wf, rows, wg_waves=4, grid_per_cu=8, nt=0):
+def _force_rows(wf, rows, wg_waves=4, grid_per_cu=8, nt=0, store_lines=1):
     for op in (wf.OP_IS, wf.OP_TO, wf.OP_TO_INPLACE, wf.OP_LOCATE):
-        wf.set_params(op, 1, -1, rows=rows, wg_waves=wg_waves, grid_per_cu=grid_per_cu, nontemporal=nt)
+        wf.set_params(op, 1, -1, rows=rows, wg_waves=wg_waves, grid_per_cu=grid_per_cu, nontemporal=nt,
+                      store_lines=store_lines)
     # (a locate over few strings takes the flat parameters)
     wf.set_params(wf.OP_LOCATE, 0, -1, rows=rows, wg_waves=wg_waves, grid_per_cu=grid_per_cu, nontemporal=nt)
 
@@ -538,7 +539,7 @@ def test_runs_of_empty_strings(wf):
 
 def test_random_shapes_and_contents(wf):
     """Random launch shapes (rows, waves per workgroup, workgroups per CU,
-    non-temporal) against random batches: long and short strings, runs of
+    non-temporal, in-place store mode) against random batches: long and short strings, runs of
     empty strings, error-free strings, strings with one late error and with
     dense errors; every operation, with and without a size hint, against
     the oracle."""
@@ -570,8 +571,9 @@ def test_random_shapes_and_contents(wf):
         wg_waves = int(rng.choice([1, 2, 4, 8, 16]))
         grid = int(rng.choice([1, 2, 8, 32, 64]))
         nt = int(rng.integers(0, 2))
-        _force_rows(wf, rows, wg_waves, grid, nt)
+        sl = (case // 2) % 2  # in-place store mode: whole lines or changed vectors
+        _force_rows(wf, rows, wg_waves, grid, nt, store_lines=sl)
         hint = int(off[-1]) if case % 2 else 0
-        _check_batch(wf, buf, off, what=f"case {case} rows={rows} waves={wg_waves} grid={grid} nt={nt}",
+        _check_batch(wf, buf, off, what=f"case {case} rows={rows} waves={wg_waves} grid={grid} nt={nt} lines={sl}",
                      hint=hint)
     wf.reset_params()

@@ -29,9 +29,10 @@ def wf():
     wf.reset_params()
 
 
-def _force_rows(wf, rows, wg_waves=4, grid_per_cu=8, nt=0):
+def _force_rows(wf, rows, wg_waves=4, grid_per_cu=8, nt=0, store_lines=1):
     for op in (wf.OP_IS, wf.OP_TO, wf.OP_TO_INPLACE, wf.OP_LOCATE):
-        wf.set_params(op, 0, -1, rows=rows, wg_waves=wg_waves, grid_per_cu=grid_per_cu, nontemporal=nt)
+        wf.set_params(op, 0, -1, rows=rows, wg_waves=wg_waves, grid_per_cu=grid_per_cu, nontemporal=nt,
+                      store_lines=store_lines)
 
 
 def _check_all(wf, s, phase_in=0, phase_out=0, what=""):
@@ -185,6 +186,28 @@ def test_launch_shapes(wf, combo):
     for rows in ROWS:
         _force_rows(wf, rows, wg_waves=wg, grid_per_cu=gpc, nt=nt)
         _check_all(wf, s, 0, 0, what=f"shape rows={rows} wg={wg} gpc={gpc} nt={nt}")
+    wf.reset_params()
+
+
+@pytest.mark.parametrize("store_lines", [1, 0])
+def test_inplace_store_modes(wf, store_lines):
+    """In-place repair in both store modes (whole 128-byte lines holding a
+    change, or only the 16-byte vectors that changed), every row count, at
+    several phases: equal to the oracle, nothing outside the string
+    written."""
+    s = W.mix(300_007, 1e-2, 81)
+    s[5000:7000] = W.all_surrogates(2000, 6)
+    want = oracle.to_well_formed(s)
+    for rows in ROWS:
+        _force_rows(wf, rows, store_lines=store_lines)
+        for ph in (0, 3, 7):
+            t, base = to_dev(s, ph, pad=8)
+            before = to_host(base)
+            wf.utf16_to_well_formed_inplace(t)
+            got = to_host(base)
+            lo = ph + 8
+            assert_same(got[lo:lo + s.size], want, f"in place rows={rows} lines={store_lines} phase={ph}")
+            assert np.array_equal(got[:lo], before[:lo]) and np.array_equal(got[lo + s.size:], before[lo + s.size:])
     wf.reset_params()
 
 
