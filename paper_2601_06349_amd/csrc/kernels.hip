@@ -902,14 +902,20 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
             } else if constexpr (OP == kOpIs) {
                 if constexpr (!BATCH) {
                     if (wave_bad) {
-                        // Every wave that sees a mismatch clears the result,
-                        // but only one in sixteen does so with a device-
-                        // coherent store (which other waves' polls observe);
-                        // the rest write through their cache, so thousands of
-                        // waves do not queue on one memory location.
+                        // Every wave that sees a mismatch clears the result;
+                        // the clearing is published with a device-coherent
+                        // store (which other waves' polls observe) when it
+                        // was found past the wave's first tile, else by one
+                        // wave in 256; the rest write through their cache.
+                        // Dense errors are found by every wave in its first
+                        // tile, at once, and thousands of coherent stores to
+                        // one word would queue; but then every wave stops
+                        // after that tile anyway. A sparse error is most
+                        // likely found past the first tile, and then it is
+                        // always published.
                         if (lane == 0 &&
                             __hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                            if ((wave & 15) == 0)
+                            if (t != tb || (wave & 255) == 0)
                                 __hip_atomic_store(a.flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             else
                                 __hip_atomic_store(a.flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
