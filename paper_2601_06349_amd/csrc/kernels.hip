@@ -885,10 +885,12 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
                     st_row<NT>(out, tl + (int64_t)r * kRowUnits, lane, lo, hi, o);
                 }
             } else if constexpr (OP == kOpToInplace) {
-                // Inside the buffer, the eight lanes of a 128-byte line store
-                // together when any of them changed, so memory sees whole-line
-                // writes rather than partial ones; unchanged lanes write back
-                // the values they read, which no other wave writes.
+                // Inside the buffer, in the line store mode the eight lanes
+                // of a 128-byte line store together when any of them changed,
+                // so memory sees whole-line writes rather than partial ones;
+                // unchanged lanes write back the values they read, which no
+                // other wave writes. In the sector mode (SS) only the lanes
+                // that changed store.
                 if (interior) {
                     if constexpr (SS) {
                         if (lane_bad)
