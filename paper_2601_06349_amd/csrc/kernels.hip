@@ -413,18 +413,24 @@ __device__ __forceinline__ uint64_t groups_in(uint64_t m, int r, int g0, int g1)
 // its count and offers its first mismatch. o_first: offsets[cursor + lane]
 // + shift (INT64_MAX past the last), cursor the first k with offsets[k] +
 // shift >= tl. start_prev: where string cursor - 1 starts, if known
-// (INT64_MIN otherwise; the locate then reads it). Returns the start of the
-// string holding unit th - 1, if known. All lanes of the wave call it
-// together.
+// (INT64_MIN otherwise; the locate then reads it). pre: the check with at
+// most 4 rows, 64 R bytes of the wave's LDS; a string whose first and last
+// groups are clean and that has groups between tests them with two reads of
+// pre[g], the number of groups before g that hold a mismatch, filled when a
+// string first needs it (otherwise, and for the locate, the middle groups'
+// masks are tested row by row). Returns the start of the string holding unit
+// th - 1, if known. All lanes of the wave call it together.
 template <int OP, int R>
 __device__ __forceinline__ int64_t span_planes(const KernelArgs &a, const int64_t *off, int64_t shift,
                                                int64_t cursor, int64_t o_first, int64_t tl, int64_t th, int lane,
-                                               const uint4 *w4, const uint64_t (&M)[R], int64_t start_prev) {
+                                               const uint4 *w4, const uint64_t (&M)[R], int64_t start_prev,
+                                               uint8_t *pre) {
     constexpr int T = kRowUnits * R;
     constexpr uint64_t kUnits = 0x0101010101010101ull;  // bit 8 j: unit j of row 7
     int64_t kb = cursor, o = o_first;
     int32_t ac = -1;               // start of string kb - 1 relative to tl (-1: before the tile)
     int64_t ac_abs = start_prev;   // ... and absolute, if known
+    bool pre_done = false;         // check: pre[] filled for this tile
     for (;;) {
         const int32_t orl = (int32_t)min(max(o - tl, (int64_t)-1), (int64_t)T + 1);
         int32_t arl = __shfl_up(orl, 1);
@@ -432,6 +438,8 @@ __device__ __forceinline__ int64_t span_planes(const KernelArgs &a, const int64_
             arl = ac;
         const int64_t k = kb + lane - 1;
         const int64_t o63 = lane_value(o, 63);
+        bool bad = false, need = false;  // check: a mismatch found / the middle groups still to test
+        int g0n = 0, g1n = 0;
         if (k >= 0 && k < a.nstr && orl > 0 && arl < T && arl < orl) {
             const int ul = max(arl, 0), uh = min(orl, T);
             const int g0 = ul >> 3, g1 = (uh - 1) >> 3;
@@ -451,14 +459,16 @@ __device__ __forceinline__ int64_t span_planes(const KernelArgs &a, const int64_
                 ce = ((((uint64_t)We.w << 32 | We.z) >> (8 * (uh & 7) + 7 - (ge >> 6))) & 1ull) != 0ull;
             }
             if constexpr (OP == kOpIs) {
-                bool bad = cs || ce || f0 || f1;
-                if (!bad && g1 - g0 >= 2) {
+                bad = cs || ce || f0 || f1;
+                if constexpr (R <= 4) {
+                    need = !bad && g1 - g0 >= 2;
+                    g0n = g0;
+                    g1n = g1;
+                } else if (!bad && g1 - g0 >= 2) {
 #pragma unroll
                     for (int r = 0; r < R; ++r)
                         bad = bad || groups_in(M[r], r, g0 + 1, g1 - 1) != 0ull;
                 }
-                if (bad)
-                    __hip_atomic_store(a.results + k, (uint8_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             } else {
                 constexpr int kNone = 0x7FFFFFFF;
                 uint32_t cnt = (uint32_t)__popcll(f0) + (uint32_t)cs + (uint32_t)ce;
@@ -496,6 +506,29 @@ __device__ __forceinline__ int64_t span_planes(const KernelArgs &a, const int64_
                 }
             }
         }
+        if constexpr (OP == kOpIs) {
+            if (__ballot(need)) {
+                // strings whose first and last groups are clean and that have
+                // groups between: pre[g] counts the mismatch groups before g
+                // (g = 64 r + lane), filled once per tile when first needed
+                if (!pre_done) {
+                    uint32_t base = 0;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(M[r] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)M[r], 0u));
+                        pre[r * 64 + lane] = (uint8_t)(base + below);  // at most 255: R <= 4
+                        base += (uint32_t)__popcll(M[r]);
+                    }
+                    wave_lds_sync();
+                    pre_done = true;
+                }
+                if (need)
+                    bad = pre[g1n] != pre[g0n + 1];
+            }
+            if (bad)
+                __hip_atomic_store(a.results + k, (uint8_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
         if (o63 >= th) {
             const int c = __popcll(__ballot(o < th));
             return c > 0 ? lane_value(o, c - 1) : ac >= 0 ? tl + ac : ac_abs;
@@ -528,6 +561,11 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
     constexpr bool kSpans = BATCH && (OP == kOpIs || OP == kOpLocate);
     __shared__ uint32_t s_bm[(BATCH && !kSpans) ? kMaxWgWaves * kWords : 1];
     __shared__ uint4 s_w4[kSpans ? kMaxWgWaves * 64 : 1];
+    // the check with at most 4 rows: counts of mismatch groups before each
+    // group, for span_planes (with 8 rows, measured slower on the 1024-unit
+    // string batch than testing the middle groups' masks)
+    constexpr bool kPre = kSpans && OP == kOpIs && R <= 4;
+    __shared__ uint8_t s_pre[kPre ? kMaxWgWaves * 64 * R : 1];
     // OP_LOCATE: per-workgroup totals, published by the last wave (batch:
     // for the one string s_loc_k that the first reporting wave names)
     __shared__ unsigned long long s_loc_first, s_loc_k, s_loc_total;
@@ -576,6 +614,7 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
 
     uint32_t *bm = (BATCH && !kSpans) ? s_bm + wslot * kWords : nullptr;
     uint4 *w4 = kSpans ? s_w4 + wslot * 64 : nullptr;
+    uint8_t *pre = kPre ? s_pre + wslot * 64 * R : nullptr;
     int64_t o_first = 0;                     // span_strings: the tile's first 64 offsets
     int64_t span_k = -1, span_start = INT64_MIN;  // start of string span_k, if known
     bool bm_dirty = true;  // LDS starts with arbitrary contents
@@ -825,7 +864,7 @@ __global__ void __launch_bounds__(1024) wf_kernel(KernelArgs a) {
                 if (any) {
                     w4[lane] = (uint4){badA, badB, prA, prB};
                     wave_lds_sync();
-                    span_start = span_planes<OP, R>(a, off, shift, ts.k0, o_first, tl, th, lane, w4, M, sp);
+                    span_start = span_planes<OP, R>(a, off, shift, ts.k0, o_first, tl, th, lane, w4, M, sp, pre);
                 } else {
                     span_start = INT64_MIN;
                 }
