@@ -160,9 +160,10 @@ def _sweep(wf, run, op, batch, size_class, calls, reps, quick, finalists=5, targ
     return best[2], best[1], default_ms
 
 
-def tune(quick=False, flat_classes=None, out=None, log=print, batch_only=False):
+def tune(quick=False, flat_classes=None, out=None, log=print, batch_only=False, batches=True):
     """Sweep launch shapes and write the cache. batch_only keeps the flat
-    entries of the existing cache and re-tunes the batch keys alone."""
+    entries of the existing cache and re-tunes the batch keys alone;
+    batches=False tunes the flat classes alone."""
     import torch
 
     import paper_2601_06349_amd as wf
@@ -218,64 +219,65 @@ def tune(quick=False, flat_classes=None, out=None, log=print, batch_only=False):
             log(f"flat {names[op]:10s} 2^{c:2d}: tuned {ms * 1e3:9.1f} us  default {dms * 1e3:9.1f} us  {params}")
     del d_in, d_outs, d_tmp
 
-    # batches: the Zipf(1.1) 4096-string workload (1.58G units), the
-    # 1,000,000 log-normal strings (98.6M units), 262,144 JavaScript-shape
-    # strings of 1024 units (268M units) and a serving-size batch of 32
-    # strings (1.2e5 units, where launch latency and the edge tiles weigh).
-    # Unknown sizes (no hint, class 40) are tuned on the first two, weighted
-    # alike; hinted calls on the one of their size (class 30: Zipf, the
-    # nearest tuned class for large batches; class 28: the 1024-unit strings;
-    # class 26: the log-normal batch; class 16: the small batch, for the
-    # smallest).
-    zb, zoff, _ = W.zipf_batch()
-    rb, roff = W.ragged_batch()
-    jb, joff = W.js_batch()
-    sb, soff = W.small_batch()
-    dev = {}
-    for label, buf, off in (("zipf_4096", zb, zoff), ("ragged_1m", rb, roff), ("js_262144", jb, joff),
-                            ("small_32", sb, soff)):
-        t_in = torch.from_numpy(buf.view(np.int16)).cuda()
-        b = off.size - 1
-        dev[label] = {"in": t_in, "off": torch.from_numpy(off).cuda(), "out": torch.empty_like(t_in),
-                      "ip": t_in.clone(), "res": torch.empty(b, dtype=torch.uint8, device="cuda"),
-                      "first": torch.empty(b, dtype=torch.int64, device="cuda"),
-                      "count": torch.empty(b, dtype=torch.int64, device="cuda"), "units": int(off[-1])}
+    if batches:
+        # batches: the Zipf(1.1) 4096-string workload (1.58G units), the
+        # 1,000,000 log-normal strings (98.6M units), 262,144 JavaScript-shape
+        # strings of 1024 units (268M units) and a serving-size batch of 32
+        # strings (1.2e5 units, where launch latency and the edge tiles weigh).
+        # Unknown sizes (no hint, class 40) are tuned on the first two, weighted
+        # alike; hinted calls on the one of their size (class 30: Zipf, the
+        # nearest tuned class for large batches; class 28: the 1024-unit strings;
+        # class 26: the log-normal batch; class 16: the small batch, for the
+        # smallest).
+        zb, zoff, _ = W.zipf_batch()
+        rb, roff = W.ragged_batch()
+        jb, joff = W.js_batch()
+        sb, soff = W.small_batch()
+        dev = {}
+        for label, buf, off in (("zipf_4096", zb, zoff), ("ragged_1m", rb, roff), ("js_262144", jb, joff),
+                                ("small_32", sb, soff)):
+            t_in = torch.from_numpy(buf.view(np.int16)).cuda()
+            b = off.size - 1
+            dev[label] = {"in": t_in, "off": torch.from_numpy(off).cuda(), "out": torch.empty_like(t_in),
+                          "ip": t_in.clone(), "res": torch.empty(b, dtype=torch.uint8, device="cuda"),
+                          "first": torch.empty(b, dtype=torch.int64, device="cuda"),
+                          "count": torch.empty(b, dtype=torch.int64, device="cuda"), "units": int(off[-1])}
 
-    def batch_call(label, op, hint):
-        d = dev[label]
-        if op == wf.OP_TO:
-            return lambda: wf.utf16wf_batch(op, d["in"], d["off"], out=d["out"], units_hint=hint)
-        if op == wf.OP_TO_INPLACE:
-            # restored before each call (untimed), so every call repairs
-            return (lambda: d["ip"].copy_(d["in"]),
-                    lambda: wf.utf16wf_batch(op, d["ip"], d["off"], out=d["ip"], units_hint=hint))
-        if op == wf.OP_LOCATE:
-            return lambda: wf.utf16wf_batch(op, d["in"], d["off"], first=d["first"], count=d["count"],
-                                            units_hint=hint)
-        return lambda: wf.utf16wf_batch(op, d["in"], d["off"], results=d["res"], units_hint=hint)
+        def batch_call(label, op, hint):
+            d = dev[label]
+            if op == wf.OP_TO:
+                return lambda: wf.utf16wf_batch(op, d["in"], d["off"], out=d["out"], units_hint=hint)
+            if op == wf.OP_TO_INPLACE:
+                # restored before each call (untimed), so every call repairs
+                return (lambda: d["ip"].copy_(d["in"]),
+                        lambda: wf.utf16wf_batch(op, d["ip"], d["off"], out=d["ip"], units_hint=hint))
+            if op == wf.OP_LOCATE:
+                return lambda: wf.utf16wf_batch(op, d["in"], d["off"], first=d["first"], count=d["count"],
+                                                units_hint=hint)
+            return lambda: wf.utf16wf_batch(op, d["in"], d["off"], results=d["res"], units_hint=hint)
 
-    keys = [("zipf_4096", int(np.floor(np.log2(dev["zipf_4096"]["units"]))), [("zipf_4096", True)]),
-            ("ragged_1m", int(np.floor(np.log2(dev["ragged_1m"]["units"]))), [("ragged_1m", True)]),
-            ("js_262144", int(np.floor(np.log2(dev["js_262144"]["units"]))), [("js_262144", True)]),
-            ("small_32", int(np.floor(np.log2(dev["small_32"]["units"]))), [("small_32", True)]),
-            ("zipf_4096 + ragged_1m, no hint", 40, [("zipf_4096", False), ("ragged_1m", False)])]
-    best_ms = {}  # (workload, op) -> its own tuned time, the targets of the no-hint class
-    for label, cls, which in keys:
-        for op in (wf.OP_TO, wf.OP_TO_INPLACE, wf.OP_IS, wf.OP_LOCATE):
-            calls = [batch_call(w, op, dev[w]["units"] if hinted else 0) for w, hinted in which]
-            targets = [best_ms[(w, op)] for w, _ in which] if cls == 40 else None
-            # short calls (the small batch) get more repetitions
-            reps_b = 5 if min(dev[w]["units"] for w, _ in which) >= 1 << 24 else 40
-            modes = (1, 0) if op == wf.OP_TO_INPLACE else (1,)
-            params, ms, dms = _sweep(wf, run, op, 1, cls, calls, reps_b, quick, targets=targets, store_modes=modes)
-            if cls != 40:
-                best_ms[(label, op)] = ms
-            entries.append({"op": op, "op_name": names[op], "batch": 1, "size_class": cls, "params": params,
-                            "tuned_ms": round(ms, 5), "default_ms": round(dms, 5), "workload": label,
-                            "units": sum(dev[w]["units"] for w, _ in which)})
-            log(f"batch {label} class {cls} {names[op]:10s}: tuned {ms:8.3f} ms  default {dms:8.3f} ms  {params}")
-    del dev
-    torch.cuda.empty_cache()
+        keys = [("zipf_4096", int(np.floor(np.log2(dev["zipf_4096"]["units"]))), [("zipf_4096", True)]),
+                ("ragged_1m", int(np.floor(np.log2(dev["ragged_1m"]["units"]))), [("ragged_1m", True)]),
+                ("js_262144", int(np.floor(np.log2(dev["js_262144"]["units"]))), [("js_262144", True)]),
+                ("small_32", int(np.floor(np.log2(dev["small_32"]["units"]))), [("small_32", True)]),
+                ("zipf_4096 + ragged_1m, no hint", 40, [("zipf_4096", False), ("ragged_1m", False)])]
+        best_ms = {}  # (workload, op) -> its own tuned time, the targets of the no-hint class
+        for label, cls, which in keys:
+            for op in (wf.OP_TO, wf.OP_TO_INPLACE, wf.OP_IS, wf.OP_LOCATE):
+                calls = [batch_call(w, op, dev[w]["units"] if hinted else 0) for w, hinted in which]
+                targets = [best_ms[(w, op)] for w, _ in which] if cls == 40 else None
+                # short calls (the small batch) get more repetitions
+                reps_b = 5 if min(dev[w]["units"] for w, _ in which) >= 1 << 24 else 40
+                modes = (1, 0) if op == wf.OP_TO_INPLACE else (1,)
+                params, ms, dms = _sweep(wf, run, op, 1, cls, calls, reps_b, quick, targets=targets, store_modes=modes)
+                if cls != 40:
+                    best_ms[(label, op)] = ms
+                entries.append({"op": op, "op_name": names[op], "batch": 1, "size_class": cls, "params": params,
+                                "tuned_ms": round(ms, 5), "default_ms": round(dms, 5), "workload": label,
+                                "units": sum(dev[w]["units"] for w, _ in which)})
+                log(f"batch {label} class {cls} {names[op]:10s}: tuned {ms:8.3f} ms  default {dms:8.3f} ms  {params}")
+        del dev
+        torch.cuda.empty_cache()
 
     data = {"device": device_key(), "created_unix": int(time.time()),
             "sweep": "quick" if quick else "full", "seconds": round(time.time() - t_start, 1),
