@@ -160,10 +160,13 @@ def _sweep(wf, run, op, batch, size_class, calls, reps, quick, finalists=5, targ
     return best[2], best[1], default_ms
 
 
-def tune(quick=False, flat_classes=None, out=None, log=print, batch_only=False, batches=True):
-    """Sweep launch shapes and write the cache. batch_only keeps the flat
-    entries of the existing cache and re-tunes the batch keys alone;
-    batches=False tunes the flat classes alone."""
+def tune(quick=False, flat_classes=None, out=None, log=print, batch_only=False, batches=True, ops=None,
+         keep=False):
+    """Sweep launch shapes and write the cache. batch_only re-tunes the batch
+    keys alone; batches=False tunes the flat classes alone; ops (names, e.g.
+    ["to_inplace"]) limits the flat sweep to those operations. With keep (and
+    always with batch_only) the existing cache's entries that were not
+    re-tuned stay in the written cache."""
     import torch
 
     import paper_2601_06349_amd as wf
@@ -171,9 +174,11 @@ def tune(quick=False, flat_classes=None, out=None, log=print, batch_only=False, 
 
     run = _timer(torch)
     entries = []
-    if batch_only:
+    old = []
+    if batch_only or keep:
         with open(out or cache_path()) as f:
-            entries = [e for e in json.load(f)["entries"] if e["batch"] == 0]
+            old = json.load(f)["entries"]
+    if batch_only:
         flat_classes = []
     if flat_classes is None:
         flat_classes = list(range(10, 29, 2)) if quick else list(range(10, 29))
@@ -189,22 +194,21 @@ def tune(quick=False, flat_classes=None, out=None, log=print, batch_only=False, 
     d_in = {v: torch.from_numpy(W.single_buffer(v, n=top, seed=4242 + i).view(np.int16)).cuda()
             for i, v in enumerate(kinds)}
     d_outs = [torch.empty_like(d_in[kinds[0]]) for _ in kinds]
-    d_tmp = [torch.empty_like(d_in[kinds[0]]) for _ in range(2)]
+    d_tmp = torch.empty_like(d_in[kinds[0]])
     res = torch.empty(4, dtype=torch.int64, device="cuda")
     for c in flat_classes:
         n = 1 << c
         reps = 10 if n >= 1 << 24 else 15
         x = {v: d_in[v][:n] for v in kinds}
         ys = [o[:n] for o in d_outs]
-        z1, z2 = d_tmp[0][:n], d_tmp[1][:n]
-        z2.copy_(x["ascii"])
+        z1 = d_tmp[:n]
         r32 = res[:1].view(torch.int32)
         calls = {
             wf.OP_TO: [(lambda a=x[v], b=ys[i]: wf.utf16_to_well_formed(a, b)) for i, v in enumerate(kinds)],
-            # in place: the 1e-2 mix, restored before each call (untimed), and
-            # a clean buffer, which the repair leaves as it is
-            wf.OP_TO_INPLACE: [(lambda: z1.copy_(x["mix1e-2"]), lambda: wf.utf16_to_well_formed_inplace(z1)),
-                               lambda: wf.utf16_to_well_formed_inplace(z2)],
+            # in place: the five kinds of content, each restored into one
+            # scratch buffer before its call (untimed), as the benchmark does
+            wf.OP_TO_INPLACE: [(lambda v=v: z1.copy_(x[v]), lambda: wf.utf16_to_well_formed_inplace(z1))
+                               for v in kinds],
             # isWellFormed: full passes over clean inputs (errors end it early)
             wf.OP_IS: [lambda: wf.utf16_is_well_formed(x["mix0"], r32),
                        lambda: wf.utf16_is_well_formed(x["ascii"], r32)],
@@ -212,6 +216,8 @@ def tune(quick=False, flat_classes=None, out=None, log=print, batch_only=False, 
                            lambda: wf.utf16_locate_ill_formed(x["mix0"])],
         }
         for op, cs in calls.items():
+            if ops is not None and names[op] not in ops:
+                continue
             modes = (1, 0) if op == wf.OP_TO_INPLACE else (1,)
             params, ms, dms = _sweep(wf, run, op, 0, c, cs, reps, quick, store_modes=modes)
             entries.append({"op": op, "op_name": names[op], "batch": 0, "size_class": c, "params": params,
@@ -279,6 +285,9 @@ def tune(quick=False, flat_classes=None, out=None, log=print, batch_only=False, 
         del dev
         torch.cuda.empty_cache()
 
+    tuned = {(e["op"], e["batch"], e["size_class"]) for e in entries}
+    entries = [e for e in old if (e["op"], e["batch"], e["size_class"]) not in tuned] + entries
+    entries.sort(key=lambda e: (e["batch"], e["size_class"], e["op"]))
     data = {"device": device_key(), "created_unix": int(time.time()),
             "sweep": "quick" if quick else "full", "seconds": round(time.time() - t_start, 1),
             "entries": entries}
@@ -296,8 +305,13 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--batch-only", action="store_true",
                     help="keep the cache's flat entries; re-tune the batch keys")
+    ap.add_argument("--ops", default=None,
+                    help="comma-separated flat operations to tune (is, to, to_inplace, locate)")
+    ap.add_argument("--no-batches", action="store_true", help="tune the flat classes alone")
+    ap.add_argument("--keep", action="store_true", help="keep the cache's entries that are not re-tuned")
     args = ap.parse_args()
-    tune(quick=args.quick, out=args.out, log=lambda m: print(m, flush=True), batch_only=args.batch_only)
+    tune(quick=args.quick, out=args.out, log=lambda m: print(m, flush=True), batch_only=args.batch_only,
+         batches=not args.no_batches, ops=args.ops.split(",") if args.ops else None, keep=args.keep)
     return 0
 
 
