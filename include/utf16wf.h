@@ -234,7 +234,9 @@ int utf16wf_copy_units(const uint16_t *in, uint16_t *out, int64_t n, void *strea
 /* Number of compute units of the current device (0 on failure). */
 int utf16wf_device_cus(void);
 
+/* Thread-local message of the last failing call. */
 const char *utf16wf_last_error(void);
+/* Version of this interface: 2 (utf16wf_params gained store_lines). */
 int utf16wf_abi_version(void);
 
 #ifdef __cplusplus
